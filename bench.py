@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Benchmark: visibilities/s for one grid + one degrid call on one MI355X.
+
+A step is one pass of the whole hot path over the wide-field workload
+(2048^2 image, L = 0.4, W = 7, x0 = 0.25, 9,999,360 visibilities from 64
+antennas in a 5 km disc, +-1 h, declination -30 deg, 1.4 GHz scaled so the
+image is Nyquist-sampled; complex N(0, 1) visibility values, N(0, 1) image):
+grid_visibilities followed by degrid_visibilities, FP32 arithmetic with FP64
+coordinates, phases and tables.  Inputs are resident in HBM before timing.
+
+Printed: one JSON line with the metric, the FP64 path's figures, per-stage
+HIP-event times, the roofline of the dominant kernel and the CPU oracle's
+throughput on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool) -> float:
+    """Algorithmic HBM bytes of one launch of a stage (what the stage must move)."""
+    b = 16 if f64 else 8            # complex
+    r = 8 if f64 else 4             # real
+    rec = 56 if f64 else 32         # binned record
+    stack = nl * Np * Np * b
+    inter = nl * N * Np * b
+    return {
+        "grid_bin": M * (2 * 24 + b + rec),          # uvw read twice, vis, records written
+        "grid_tiles": M * rec + stack,                # records in, stack out
+        "grid_fft_v": stack + inter,                  # stack in, intermediate out
+        "grid_fft_u": inter + 2 * N * N * r,          # intermediate, correction in, map out
+        "degrid_bin": M * (2 * 24 + rec),
+        "degrid_fft_p": 2 * N * N * r + inter,        # image, correction in, intermediate out
+        "degrid_fft_q": inter + stack,
+        "degrid_tiles": stack + M * rec + M * b,      # stack, records in, visibilities out
+    }[st]
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "fft.hpp", "common.hpp", "wsgrid.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2101_11172_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, prec: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    return t.get("per_launch_bytes", {}).get(f"{kernel}:{prec}")
+
+
+def cpu_baseline(w: dict, n_sample: int) -> dict:
+    """The FP64 oracle, as written, timed on a bounded sample and scaled to the full call.
+
+    Per-visibility steps are timed at two sample sizes (n and 2n) so that their
+    fixed per-layer part (the oracle grids each layer through a full N'^2
+    bincount) and their per-visibility slope are separated; one layer's
+    transform and a slice of the correction map are timed and scaled.
+    """
+    import numpy as np
+
+    from oracle import wstack
+    from oracle.kernel_design import least_misfit
+    from oracle.plan import make_plan
+
+    plan = make_plan(w["N"], w["L"], w["W"], w["x0"], w["wmax"])
+    lm = least_misfit(w["W"], w["x0"])
+    M, nl = w["uvw"].shape[0], plan.n_layers
+    z = plan.z()
+    measured = 0.0
+
+    def grid_vis(n):
+        t0 = time.perf_counter()
+        gi = wstack.grid_prepare(plan, lm, w["uvw"][:n], w["vis"][:n].astype(np.complex128))
+        G = None
+        for t in range(plan.t_lo, plan.t_hi + 1):
+            G = wstack.grid_layer(plan, gi, t)
+        return time.perf_counter() - t0, G
+
+    stack = np.zeros((nl, plan.Nprime, plan.Nprime), dtype=np.complex128)   # untouched pages: zero page
+
+    def degrid_vis(n):
+        t0 = time.perf_counter()
+        wstack.degrid_correlate(plan, lm, w["uvw"][:n], stack)
+        return time.perf_counter() - t0
+
+    n1, n2 = n_sample, 2 * n_sample
+    tg1, _ = grid_vis(n1)
+    tg2, G = grid_vis(n2)
+    td1, td2 = degrid_vis(n1), degrid_vis(n2)
+    measured += tg1 + tg2 + td1 + td2
+    g_slope, d_slope = max(tg2 - tg1, 0.0) / (n2 - n1), max(td2 - td1, 0.0) / (n2 - n1)
+    g_fixed, d_fixed = max(tg1 - g_slope * n1, 0.0), max(td1 - d_slope * n1, 0.0)
+    t0 = time.perf_counter()
+    wstack.layer_image(plan, G, plan.t_hi, z)
+    t_grid_layer = time.perf_counter() - t0
+    n_pix = 8192 * 4
+    t0 = time.perf_counter()
+    lm.h(z.ravel()[:n_pix])
+    t_pix = time.perf_counter() - t0
+    t_corr = t_pix * (plan.N * plan.N / n_pix)
+    g = np.ones((plan.N, plan.N))
+    t0 = time.perf_counter()
+    wstack.degrid_layer(plan, g, plan.t_hi, z)
+    t_degrid_layer = time.perf_counter() - t0
+    del stack
+    measured += t_grid_layer + t_pix + t_degrid_layer
+    t_grid = g_fixed + g_slope * M + nl * t_grid_layer + t_corr
+    t_degrid = d_fixed + d_slope * M + nl * t_degrid_layer + t_corr
+    return {
+        "value": M / (t_grid + t_degrid),
+        "unit": "visibilities/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle per-visibility steps (fold, phase, weights, w-spreading and uv-gridding into all "
+                   f"{nl} layers; 3-D correlation) on the first {n1} and {n2} visibilities (fixed + per-"
+                   f"visibility fit), one layer's {plan.Nprime}^2 IFFT/crop/w-screen and one layer's pad/FFT, "
+                   f"h_z on {n_pix} pixels; scaled to {M} visibilities, {nl} layers, {plan.N}^2 pixels; "
+                   f"{measured:.1f} s measured, numpy single-threaded"),
+        "est_s_per_call": {"grid": t_grid, "degrid": t_degrid},
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dumps", type=int, default=4960, help="time samples (M = 2016 x dumps)")
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=10000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the path is built and measured on a single MI355X "
+              "(multi-GPU sharding over w-layers is a design, not a measured run)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2101_11172_amd import inputs, wsgrid
+
+    dev = torch.device("cuda", 0)
+    log("generating the wide-field workload")
+    w = inputs.workload("widefield", n_dumps=args.dumps, vis_dtype=np.complex64)
+    N, L, W, x0, wmax = w["N"], w["L"], w["W"], w["x0"], w["wmax"]
+    M = w["uvw"].shape[0]
+    plan = wsgrid.Plan(N, L, W, x0, wmax, device=dev)
+    info = plan.info
+    Np, nl = info["Nprime"], info["n_layers"]
+    log(f"M={M} N={N} N'={Np} layers={nl} E={info['E']:.3e}")
+    uvw = torch.from_numpy(w["uvw"]).to(dev)
+    vis32 = torch.from_numpy(w["vis"]).to(dev)
+    img32 = torch.from_numpy(inputs.random_image(N, 5).astype(np.float32)).to(dev)
+    out_img32 = torch.empty((N, N), dtype=torch.float32, device=dev)
+    out_vis32 = torch.empty(M, dtype=torch.complex64, device=dev)
+
+    def step32():
+        plan.grid(uvw, vis32, out=out_img32)
+        plan.degrid(uvw, img32, out=out_vis32)
+
+    for i in range(args.warmup):
+        step32()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    wsgrid.wsg_stage_times()            # clear
+    wsgrid.wsg_stage_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step32()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wsgrid.wsg_stage_timing(False)
+    stages32 = wsgrid.wsg_stage_times()
+    ms32 = (t1 - t0) * 1e3 / args.steps
+    log(f"fp32: {ms32:.3f} ms/step, {M / (ms32 * 1e-3):.4e} vis/s")
+    skipped = plan.skipped(wsgrid.WSG_F32)
+
+    # FP64 path on the same data
+    uvw64_vis = vis32.to(torch.complex128)
+    img64 = img32.double()
+    out_img64 = torch.empty((N, N), dtype=torch.float64, device=dev)
+    out_vis64 = torch.empty(M, dtype=torch.complex128, device=dev)
+
+    def step64():
+        plan.grid(uvw, uvw64_vis, out=out_img64)
+        plan.degrid(uvw, img64, out=out_vis64)
+
+    step64()
+    torch.cuda.synchronize()
+    wsgrid.wsg_stage_times()
+    wsgrid.wsg_stage_timing(True)
+    t0 = time.perf_counter()
+    for i in range(args.fp64_steps):
+        step64()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wsgrid.wsg_stage_timing(False)
+    stages64 = wsgrid.wsg_stage_times()
+    ms64 = (t1 - t0) * 1e3 / args.fp64_steps
+    log(f"fp64: {ms64:.3f} ms/step, {M / (ms64 * 1e-3):.4e} vis/s")
+
+    def relrms(a, b):
+        return float(torch.linalg.vector_norm(a.double() - b.double()) / torch.linalg.vector_norm(b.double()))
+
+    acc = {"grid": relrms(out_img32, out_img64),
+           "degrid": relrms(out_vis32.to(torch.complex128), out_vis64)}
+
+    def stage_table(stages, f64):
+        tab = {}
+        for name, (ms, n) in stages.items():
+            if n == 0:
+                continue
+            per = ms / n
+            nbytes = stage_bytes(name, M, N, Np, nl, f64)
+            tab[name] = {"ms": per, "launches": n, "alg_bytes": nbytes, "alg_GBps": nbytes / (per * 1e-3) / 1e9}
+        return tab
+
+    tab32 = stage_table(stages32, False)
+    tab64 = stage_table(stages64, True)
+    dom = max(tab32, key=lambda k: tab32[k]["ms"])
+    d = tab32[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic_for(dom, "f32"),
+                "alg_bytes_per_launch": d["alg_bytes"], "ms_per_launch": d["ms"]}
+    total_alg = sum(stage_bytes(s, M, N, Np, nl, False) for s in tab32)
+    result = {
+        "metric": "visibilities/s grid+degrid at W=7,x0=0.25, FP32 vs FP64, at <=1e-6 DFT error",
+        "value": M / (ms32 * 1e-3),
+        "unit": "visibilities/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"wide-field single channel: {N}x{N} image, L={L}, W={W}, x0={x0}, {M} "
+                                f"visibilities (64 antennas in a 5 km disc, +-1 h tracks, dec -30, 1.4 GHz, "
+                                f"uvw scaled to a Nyquist-sampled image), {nl} w-layers, N'={Np}"),
+                   "N": N, "L": L, "W": W, "x0": x0, "visibilities": M, "w_layers": nl, "fft_size": Np},
+        "roofline": roofline,
+        "whole_step_alg_GBps": total_alg / (ms32 * 1e-3) / 1e9,
+        "fp64": {"value": M / (ms64 * 1e-3), "ms_per_step": ms64, "stages": tab64},
+        "fp32_vs_fp64_rel_rms": acc,
+        "stages": tab32,
+        "skipped": skipped,
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        w64 = dict(w)
+        result["cpu_baseline"] = cpu_baseline(w64, args.cpu_sample)
+        log(f"cpu oracle: {result['cpu_baseline']['value']:.4e} vis/s")
+    print(json.dumps(result), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

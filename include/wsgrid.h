@@ -1,0 +1,161 @@
+/*
+ * wsgrid.h -- improved W-stacking gridding and degridding on one MI355X (gfx950).
+ *
+ * Implements the two operators of Ye, Gull, Tan & Nikolic, "High accuracy wide
+ * field imaging method in radio interferometry" (MNRAS 2021):
+ *
+ *   grid    (Algorithm 5): visibilities -> real dirty map
+ *       D[j][i] ~= h_x h_y h_z * Re sum_t [IFFT2 G_t](i, j) exp(+i 2 pi t z_ji),
+ *       G_t = sum_k V_k exp(+i 2 pi w_k (n0 - 1)) C(r - u'_k) C(s - v'_k) C(t - w'_k)
+ *       (Sec. 5.2 eqs. gridded-dirty-map and gridded_vis, Sec. 5.4);
+ *   degrid  (Algorithm 6): real model image -> visibilities, the exact adjoint.
+ *
+ * Both approximate the direct Fourier pair of eq. fourier_visibility
+ *     V_k = sum_ji f_ji exp[-i 2 pi (u_k l_i + v_k m_j + w_k (n_ji - 1))],
+ *     D_ji = Re sum_k V_k exp[+i 2 pi (u_k l_i + v_k m_j + w_k (n_ji - 1))],
+ * with RMS relative error about sqrt(3) E(W, x0) (Sec. 6.3), E the 1-D error
+ * bound of eq. norm_bound for the least-misfit functions C, h (Sec. 3.3).
+ *
+ * Conventions shared by every entry point:
+ *   - image f / dirty map D: N x N real, row-major, row j <-> m_j, column i <-> l_i,
+ *     l_i = (i - N/2) L/N (same for m);  f is I/n (Sec. 5.2); no 1/M weights.
+ *   - uvw: M x 3 float64, row-major (u, v, w) in wavelengths, any sign and size
+ *     (u, v are taken modulo the FFT grid; Sec. 5.2).  w < 0 is folded to
+ *     (-u, -v, -w, conj V) (Sec. 5.4).  |w| > wmax (or a non-finite coordinate)
+ *     is skipped: grid ignores it, degrid returns 0 for it.
+ *   - vis: M complex values, interleaved (re, im): complex64 for WSG_F32,
+ *     complex128 for WSG_F64.  Image/dirty: float32 for WSG_F32, float64 for WSG_F64.
+ *   - all array pointers given to grid_visibilities / degrid_visibilities are
+ *     HIP device pointers owned by the caller; the call only enqueues work on
+ *     `stream` (a hipStream_t, NULL = default stream) and returns.
+ *   - return value 0 on success, or a negative WSG_E* code; the message is in
+ *     grid_last_error() (thread-local).
+ */
+#ifndef WSGRID_H
+#define WSGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wsg_plan wsg_plan;
+
+enum { WSG_F32 = 0, WSG_F64 = 1 };
+
+enum {
+    WSG_OK = 0,
+    WSG_EINVAL = -1,      /* bad argument (size, precision, null pointer, plan)   */
+    WSG_EWORKSPACE = -2,  /* workspace smaller than grid_workspace_bytes()        */
+    WSG_ENOMEM = -3,      /* host allocation failed                               */
+    WSG_EHIP = -4         /* HIP runtime error (no device, launch failure, ...)   */
+};
+
+/*
+ * Create a plan for an N x N image spanning L in direction cosine (l, m in
+ * [-L/2, L/2)), gridding width W in u, v and w, cropping parameter x0 (= y0 =
+ * z0, Sec. 6.2) and largest |w| = wmax wavelengths.
+ *   - FFT length N' = N / (2 x0) (Algorithm 1); must be a power of two in
+ *     [64, 8192].
+ *   - n_scale = (1 - n_min) / (2 z0), n0 = 1 - z0 n_scale (eq. n_params).
+ *   - w-layers t = t_lo .. t_hi with t_lo = floor(W/2) - W + 1 and
+ *     t_hi = floor(n_scale wmax + W/2) (Algorithm 5 step 1; every layer a
+ *     folded visibility can touch).
+ *   - designs the least-misfit C, h for (W, x0) in float64 on the host
+ *     (Sec. 3.3, eqs. csum2 / norm_bound) and uploads the kernel polynomials,
+ *     the per-pixel correction h_x h_y h_z (Algorithm 5 step 5) and the FFT
+ *     twiddles to the current HIP device (blocking, ~N^2 x 12 bytes).
+ * Valid ranges: N even, 1 <= W <= 16, 0 < x0 <= 1/2, 0 < L < sqrt(2), wmax >= 0.
+ * Returns NULL on error (see grid_last_error()).  The plan is immutable and may
+ * be used from several threads with distinct workspaces; it is bound to the
+ * device that was current at creation.
+ */
+wsg_plan* grid_create(int N, double L, int W, double x0, double wmax);
+
+/* Free a plan and its device tables (blocking).  NULL is ignored. */
+void grid_destroy(wsg_plan* plan);
+
+/*
+ * Plan parameters (any output pointer may be NULL): FFT length N', first
+ * layer t_lo, number of layers, n0, n_scale, and the design's error bound E.
+ */
+int grid_plan_info(const wsg_plan* plan, int* Nprime, int* t_lo, int* n_layers,
+                   double* n0, double* n_scale, double* E);
+
+/*
+ * Device workspace (bytes) that one grid_visibilities or degrid_visibilities
+ * call with M visibilities at precision `prec` needs: the w-layer stack
+ * (n_layers N'^2 complex), the FFT intermediate (n_layers N N' complex), the
+ * binned visibility records (M records) and bin tables.  0 on a bad argument.
+ */
+size_t grid_workspace_bytes(const wsg_plan* plan, int prec, int64_t M);
+
+/*
+ * Dirty map by Algorithm 5.
+ *   uvw   [M][3] float64 device;  vis [M] complex (prec) device;
+ *   dirty [N][N] real (prec) device, overwritten;
+ *   ws    device workspace of ws_bytes >= grid_workspace_bytes(plan, prec, M),
+ *         contents on entry ignored (the call owns it until the stream reaches
+ *         the end of the call's work).
+ * M = 0 gives an all-zero map (uvw and vis may then be NULL).
+ */
+int grid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw,
+                      const void* vis, void* dirty, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Model visibilities by Algorithm 6 (exact adjoint of grid_visibilities under
+ * Re <., .> on visibilities and <., .> on real images).
+ *   uvw [M][3] float64 device;  image [N][N] real (prec) device;
+ *   vis [M] complex (prec) device, overwritten;  ws as for grid_visibilities.
+ * M = 0 does nothing but the layer transforms (uvw and vis may then be NULL).
+ */
+int degrid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw,
+                        const void* image, void* vis, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Number of visibilities skipped (|w| > wmax or non-finite) by the last call
+ * that used workspace `ws`.  Waits for `stream`.  Returns < 0 on error.
+ */
+int64_t grid_skipped(const wsg_plan* plan, const void* ws, void* stream);
+
+/*
+ * Measurement aid.  While enabled on the calling thread, every grid/degrid call
+ * records HIP events on its stream around each stage:
+ *   0 grid binning (fold, count, scan, scatter)   4 degrid binning
+ *   1 grid 3-D scatter tiles                     5 degrid FFT pass along p (+ w-screen)
+ *   2 grid FFT pass along v (+ crop, transpose)  6 degrid FFT pass along q
+ *   3 grid FFT pass along u (+ w-screen, sum)    7 degrid 3-D gather tiles
+ * wsg_stage_times() waits for the recorded events, writes the summed
+ * milliseconds and launch counts of the first n stages (either pointer may be
+ * NULL), clears the record and returns WSG_NSTAGES (or < 0 on error).
+ */
+#define WSG_NSTAGES 8
+void wsg_stage_timing(int enable);
+int wsg_stage_times(double* ms, int* launches, int n);
+
+/* Message of the last error on this thread ("" if none). */
+const char* grid_last_error(void);
+
+/*
+ * Host-only inspection of the library's own least-misfit design (no GPU use):
+ * for width W and cropping x0, writes c_a(nu_k) = C(a - (W-1)/2 - nu_k) for the
+ * n_nu points nu (each in [-1/2, 1/2]) to c_out[k*W + a] (from the fitted
+ * kernel polynomials the device evaluates), h(x_k) for the n_x points x (|x| <=
+ * 1/2) to h_out, and E to *E_out (any output may be NULL when its count is 0).
+ */
+int wsg_design_eval(int W, double x0, int n_nu, const double* nu, double* c_out,
+                    int n_x, const double* x, double* h_out, double* E_out);
+
+/*
+ * Host-only planner (no GPU use): the values grid_create would use.
+ */
+int wsg_plan_params(int N, double L, int W, double x0, double wmax, int* Nprime,
+                    int* t_lo, int* t_hi, double* n0, double* n_scale);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WSGRID_H */

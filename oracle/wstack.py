@@ -16,8 +16,13 @@ Conventions (readings listed in the design doc):
   (eq. fourier_visibility); no natural weights 1/M; the image is f = I/n;
 * Hermitian fold (Sec. 5.4): a visibility with w < 0 is replaced by its conjugate
   at (-u, -v, -w); visibilities with |w| > w_max are skipped (degrid returns 0).
+
+``grid`` and ``degrid`` are compositions of the step functions below, which
+follow the algorithms' numbered steps.
 """
 from __future__ import annotations
+
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -46,6 +51,11 @@ def _normalised(plan: Plan, uvw_f: np.ndarray):
     return up, vp, wp
 
 
+def _weights(lm: LeastMisfit, xi: np.ndarray, W: int):
+    first, nu = support(xi, W)
+    return first, lm.c(nu)                      # [M], [M, W]
+
+
 def correction(plan: Plan, lm: LeastMisfit) -> np.ndarray:
     """h_x(x) h_y(y) h_z(z(x, y)) on the [j, i] pixel grid (Algorithm 5 step 5)."""
     hx = lm.h(plan.pixel_x())
@@ -53,101 +63,132 @@ def correction(plan: Plan, lm: LeastMisfit) -> np.ndarray:
     return hx[None, :] * hx[:, None] * hz
 
 
-def _weights(lm: LeastMisfit, xi: np.ndarray, W: int):
-    first, nu = support(xi, W)
-    return first, lm.c(nu)                      # [M], [M, W]
+def _crop(plan: Plan) -> np.ndarray:
+    """FFT bins of image indices 0 ... N-1: (i - N/2) mod N' (Algorithm 5 step 3c)."""
+    return (np.arange(plan.N) - plan.N // 2) % plan.Nprime
 
 
-def grid(plan: Plan, lm: LeastMisfit, uvw, vis, dump: dict | None = None) -> np.ndarray:
-    """Dirty map by Algorithm 5.  Returns the real [N, N] map."""
-    W, Np, N = plan.W, plan.Nprime, plan.N
+# ---------------------------------------------------------------- Algorithm 5
+
+@dataclass
+class GridInput:
+    """Folded, normalised visibilities with their phase and kernel weights."""
+    Vh: np.ndarray          # V exp[i 2 pi w (n0 - 1)]
+    t_first: np.ndarray
+    cz: np.ndarray
+    r_first: np.ndarray
+    cx: np.ndarray
+    s_first: np.ndarray
+    cy: np.ndarray
+
+
+def grid_prepare(plan: Plan, lm: LeastMisfit, uvw, vis) -> GridInput:
+    """Fold (Sec. 5.4), skip |w| > w_max, multiply by exp[i 2 pi w (n0 - 1)] (step 2),
+    and evaluate the W weights per axis."""
+    W = plan.W
     uvw_f, neg = _fold(uvw)
     V = np.asarray(vis, dtype=np.complex128).reshape(-1)
     V = np.where(neg, np.conj(V), V)
     keep = uvw_f[:, 2] <= plan.wmax
     uvw_f, V = uvw_f[keep], V[keep]
     up, vp, wp = _normalised(plan, uvw_f)
-
-    # Step 2: multiply by exp[i 2 pi w (n0 - 1)], with n0 - 1 = -z0 n_scale (eq. n_params),
-    # and spread over the W_z layers with weights C_z(t - w').
+    # n0 - 1 = -z0 n_scale (eq. n_params)
     Vh = V * np.exp(2j * np.pi * uvw_f[:, 2] * (-plan.z0 * plan.n_scale))
     t_first, cz = _weights(lm, wp, W)
     r_first, cx = _weights(lm, up, W)
     s_first, cy = _weights(lm, vp, W)
+    return GridInput(Vh, t_first, cz, r_first, cx, s_first, cy)
 
+
+def grid_layer(plan: Plan, gi: GridInput, t: int) -> np.ndarray:
+    """Steps 2-3a for layer t: values assigned to the layer with weight C_z(t - w'),
+    then 2-D convolutional gridding with C_x, C_y.  Returns G_t [s, r]."""
+    W, Np = plan.W, plan.Nprime
+    c_idx = t - gi.t_first
+    k = np.nonzero((c_idx >= 0) & (c_idx < W))[0]
+    if k.size == 0:
+        return np.zeros((Np, Np), dtype=np.complex128)
+    val = gi.Vh[k] * gi.cz[k, c_idx[k]]
+    rr = (gi.r_first[k, None] + np.arange(W)[None, :]) % Np          # [nk, W]
+    ss = (gi.s_first[k, None] + np.arange(W)[None, :]) % Np
+    contrib = val[:, None, None] * gi.cy[k, :, None] * gi.cx[k, None, :]   # [nk, Wy, Wx]
+    flat = (ss[:, :, None] * Np + rr[:, None, :]).ravel()
+    return (np.bincount(flat, weights=contrib.real.ravel(), minlength=Np * Np)
+            + 1j * np.bincount(flat, weights=contrib.imag.ravel(), minlength=Np * Np)).reshape(Np, Np)
+
+
+def layer_image(plan: Plan, G: np.ndarray, t: int, z: np.ndarray) -> np.ndarray:
+    """Steps 3b-3d: unnormalised 2-D IFFT, crop, phase exp(i 2 pi t z)."""
+    Np = plan.Nprime
+    crop = _crop(plan)
+    P = np.fft.ifft2(G) * (Np * Np)
+    return P[np.ix_(crop, crop)] * np.exp(2j * np.pi * t * z)
+
+
+def grid(plan: Plan, lm: LeastMisfit, uvw, vis, dump: dict | None = None) -> np.ndarray:
+    """Dirty map by Algorithm 5.  Returns the real [N, N] map."""
+    gi = grid_prepare(plan, lm, uvw, vis)
     z = plan.z()
-    acc = np.zeros((N, N), dtype=np.complex128)
-    crop = (np.arange(N) - N // 2) % Np
-    stack = np.zeros((plan.n_layers, Np, Np), dtype=np.complex128) if dump is not None else None
+    acc = np.zeros((plan.N, plan.N), dtype=np.complex128)
+    stack = [] if dump is not None else None
     for t in range(plan.t_lo, plan.t_hi + 1):
-        # visibilities assigned to layer t and their w-weights
-        c_idx = t - t_first
-        sel = (c_idx >= 0) & (c_idx < W)
-        k = np.nonzero(sel)[0]
-        G = np.zeros((Np, Np), dtype=np.complex128)
-        if k.size:
-            val = Vh[k] * cz[k, c_idx[k]]
-            # Step 3a: 2-D convolutional gridding with C_x, C_y
-            rr = (r_first[k, None] + np.arange(W)[None, :]) % Np        # [nk, W]
-            ss = (s_first[k, None] + np.arange(W)[None, :]) % Np
-            contrib = val[:, None, None] * cy[k, :, None] * cx[k, None, :]   # [nk, Wy, Wx]
-            flat = (ss[:, :, None] * Np + rr[:, None, :]).ravel()
-            G = (np.bincount(flat, weights=contrib.real.ravel(), minlength=Np * Np)
-                 + 1j * np.bincount(flat, weights=contrib.imag.ravel(), minlength=Np * Np)
-                 ).reshape(Np, Np)
+        G = grid_layer(plan, gi, t)
         if stack is not None:
-            stack[t - plan.t_lo] = G
-        # Step 3b: unnormalised 2-D inverse FFT;  3c: crop;  3d: phase exp(i 2 pi t z)
-        P = np.fft.ifft2(G) * (Np * Np)
-        P = P[np.ix_(crop, crop)]
-        # Step 4: accumulate
-        acc += P * np.exp(2j * np.pi * t * z)
-    # Step 5: 3-D gridding correction, real part
-    corr = correction(plan, lm)
+            stack.append(G)
+        acc += layer_image(plan, G, t, z)              # step 4: accumulate
+    corr = correction(plan, lm)                         # step 5
     if dump is not None:
-        dump["stack"] = stack
+        dump["stack"] = np.array(stack)
         dump["acc"] = acc
         dump["corr"] = corr
     return (acc * corr).real
 
 
-def degrid(plan: Plan, lm: LeastMisfit, uvw, image, dump: dict | None = None) -> np.ndarray:
-    """Model visibilities by Algorithm 6.  Returns complex [M]."""
-    W, Np, N = plan.W, plan.Nprime, plan.N
-    f = np.asarray(image, dtype=np.float64).reshape(N, N)
-    # Step 2: multiply by the 3-D correction
-    corr = correction(plan, lm)
-    g = f * corr
-    z = plan.z()
-    crop = (np.arange(N) - N // 2) % Np
-    stack = np.zeros((plan.n_layers, Np, Np), dtype=np.complex128)
-    for t in range(plan.t_lo, plan.t_hi + 1):
-        # Step 3a: phase exp(-i 2 pi t z);  3b: zero pad;  3c: unnormalised 2-D FFT
-        pad = np.zeros((Np, Np), dtype=np.complex128)
-        pad[np.ix_(crop, crop)] = g * np.exp(-2j * np.pi * t * z)
-        stack[t - plan.t_lo] = np.fft.fft2(pad)
-    if dump is not None:
-        dump["stack"] = stack
+# ---------------------------------------------------------------- Algorithm 6
 
+def degrid_layer(plan: Plan, g: np.ndarray, t: int, z: np.ndarray) -> np.ndarray:
+    """Steps 3a-3c for layer t: phase exp(-i 2 pi t z), zero pad, unnormalised 2-D FFT."""
+    Np = plan.Nprime
+    crop = _crop(plan)
+    pad = np.zeros((Np, Np), dtype=np.complex128)
+    pad[np.ix_(crop, crop)] = g * np.exp(-2j * np.pi * t * z)
+    return np.fft.fft2(pad)
+
+
+def degrid_correlate(plan: Plan, lm: LeastMisfit, uvw, stack: np.ndarray) -> np.ndarray:
+    """Steps 4-5: 3-D correlation with C_x C_y C_z, phase exp[-i 2 pi w (n0 - 1)],
+    conjugate for folded visibilities (Sec. 5.4)."""
+    W, Np = plan.W, plan.Nprime
     uvw_f, neg = _fold(uvw)
-    M = uvw_f.shape[0]
-    out = np.zeros(M, dtype=np.complex128)
+    out = np.zeros(uvw_f.shape[0], dtype=np.complex128)
     keep = np.nonzero(uvw_f[:, 2] <= plan.wmax)[0]
+    aW = np.arange(W)
     for lo in range(0, keep.size, 4096):
         k = keep[lo:lo + 4096]
         up, vp, wp = _normalised(plan, uvw_f[k])
         t_first, cz = _weights(lm, wp, W)
         r_first, cx = _weights(lm, up, W)
         s_first, cy = _weights(lm, vp, W)
-        # Step 4: 3-D correlation with C_x C_y C_z
-        aW = np.arange(W)
         tt = (t_first[:, None] + aW[None, :]) - plan.t_lo                 # [nk, W]
         ss = (s_first[:, None] + aW[None, :]) % Np
         rr = (r_first[:, None] + aW[None, :]) % Np
         vals = stack[tt[:, :, None, None], ss[:, None, :, None], rr[:, None, None, :]]
         wgt = cz[:, :, None, None] * cy[:, None, :, None] * cx[:, None, None, :]
         acc = np.sum(vals * wgt, axis=(1, 2, 3))
-        # Step 5: phase exp[-i 2 pi w (n0 - 1)]
         acc = acc * np.exp(-2j * np.pi * uvw_f[k, 2] * (-plan.z0 * plan.n_scale))
         out[k] = np.where(neg[k], np.conj(acc), acc)
     return out
+
+
+def degrid(plan: Plan, lm: LeastMisfit, uvw, image, dump: dict | None = None) -> np.ndarray:
+    """Model visibilities by Algorithm 6.  Returns complex [M]."""
+    N, Np = plan.N, plan.Nprime
+    f = np.asarray(image, dtype=np.float64).reshape(N, N)
+    g = f * correction(plan, lm)                         # step 2
+    z = plan.z()
+    stack = np.zeros((plan.n_layers, Np, Np), dtype=np.complex128)
+    for t in range(plan.t_lo, plan.t_hi + 1):            # step 3
+        stack[t - plan.t_lo] = degrid_layer(plan, g, t, z)
+    if dump is not None:
+        dump["stack"] = stack
+    return degrid_correlate(plan, lm, uvw, stack)        # steps 4-5

@@ -1,0 +1,510 @@
+// C-ABI of the wsgrid library: plans, workspace layout and the launch sequences
+// of Algorithm 5 (grid) and Algorithm 6 (degrid) on one gfx950 device.
+//
+// grid_visibilities:   bin (count, scan, scatter) -> k_grid_tiles (3-D scatter,
+//                      stack [t][r][s]) -> k_grid_fft_a (IFFT along s, crop,
+//                      transpose) -> k_grid_fft_b (IFFT along r, crop, w-screen,
+//                      sum over layers, correction) -> dirty [N][N]
+// degrid_visibilities: bin -> k_degrid_fft_b (correction, w-screen, pad, FFT
+//                      along p) -> k_degrid_fft_a (pad, FFT along q) ->
+//                      k_degrid_tiles (3-D gather, phase, fold) -> vis [M]
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "../../include/wsgrid.h"
+#include "design.hpp"
+#include "kernels.hpp"
+
+using namespace wsg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define WSG_HIP(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(WSG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxBins = 4096 * 1024;   // limit of the three-kernel scan
+
+// per-thread stage timing (wsg_stage_timing / wsg_stage_times)
+struct StageEvent {
+    int stage;
+    hipEvent_t a, b;
+};
+thread_local bool g_timing = false;
+thread_local std::vector<StageEvent> g_events;
+
+struct StageMark {
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageMark(hipStream_t s_, int st) : s(s_), stage(st) {
+        if (g_timing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+    }
+    ~StageMark() {
+        if (!a) return;
+        hipEvent_t b = nullptr;
+        if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess)
+            g_events.push_back({stage, a, b});
+        else
+            (void)hipEventDestroy(a);
+    }
+};
+
+}  // namespace
+
+struct wsg_plan {
+    PlanParams pp;
+    KernelDesign kd;
+    int device = -1;
+    int log2_np = 0;
+    int nbr = 0, nbs = 0, nbt = 0;
+    double* poly64 = nullptr;
+    float* poly32 = nullptr;
+    double* corr64 = nullptr;
+    float* corr32 = nullptr;
+    cpx<double>* tw64 = nullptr;
+    cpx<float>* tw32 = nullptr;
+
+    int nbins() const { return nbr * nbs * nbt; }
+};
+
+namespace {
+
+struct Layout {
+    size_t stack, inter, rec, count, start, cursor, bsums, skipped, total;
+    int nbins, nscan;
+};
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout layout_of(const wsg_plan* p, int prec, int64_t M) {
+    Layout L{};
+    const size_t cs = prec == WSG_F32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
+    const size_t rs = prec == WSG_F32 ? sizeof(Rec<float>) : sizeof(Rec<double>);
+    const size_t Np = size_t(p->pp.Nprime), N = size_t(p->pp.N), nl = size_t(p->pp.n_layers());
+    L.nbins = p->nbins();
+    L.nscan = (L.nbins + 1023) / 1024;
+    // the skipped counter sits at offset 0 whatever M and the precision
+    size_t off = 0;
+    L.skipped = off; off += 256;
+    L.count = off;   off += al256(size_t(L.nbins) * 4);
+    L.start = off;   off += al256(size_t(L.nbins + 1) * 4);
+    L.cursor = off;  off += al256(size_t(L.nbins) * 4);
+    L.bsums = off;   off += al256(size_t(L.nscan) * 4);
+    L.stack = off;   off += al256(nl * Np * Np * cs);
+    L.inter = off;   off += al256(nl * N * Np * cs);
+    L.rec = off;     off += al256(size_t(M) * rs);
+    L.total = off;
+    return L;
+}
+
+DevParams dev_params(const wsg_plan* p) {
+    DevParams P{};
+    P.N = p->pp.N;
+    P.Np = p->pp.Nprime;
+    P.W = p->pp.W;
+    P.n_layers = p->pp.n_layers();
+    P.t_lo = p->pp.t_lo;
+    P.nbr = p->nbr;
+    P.nbs = p->nbs;
+    P.nbt = p->nbt;
+    P.degree = p->kd.degree;
+    P.umul = p->pp.l_max / p->pp.x0;
+    P.nscale = p->pp.n_scale;
+    P.z0 = p->pp.x0;
+    P.wmax = p->pp.wmax;
+    P.dl = p->pp.L / p->pp.N;
+    return P;
+}
+
+template <typename T>
+void fill(T* ptr, size_t n, T v, hipStream_t s) {
+    if (n == 0) return;
+    size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fill<T>, dim3(unsigned(blocks)), dim3(256), 0, s, ptr, n, v);
+}
+
+void scan(const uint32_t* count, uint32_t* start, uint32_t* bsums, int n, hipStream_t s) {
+    const int nb = (n + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, count, start, n, bsums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb, start + n);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, s, start, n, (const uint32_t*)bsums);
+}
+
+// ---- compile-time dispatch over W and log2 N' ----
+
+template <typename R, int W>
+void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* start, const DevParams& P,
+                    const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
+    if (grid)
+        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, P, coef, stack);
+    else
+        hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, P, coef,
+                           (const cpx<R>*)stack, vis);
+}
+
+template <typename R>
+void launch_tiles(bool grid, int W, int nblocks, const Rec<R>* rec, const uint32_t* start, const DevParams& P,
+                  const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
+    switch (W) {
+#define WSG_W(w) \
+    case w: launch_tiles_w<R, w>(grid, nblocks, rec, start, P, coef, stack, vis, s); break;
+        WSG_W(1) WSG_W(2) WSG_W(3) WSG_W(4) WSG_W(5) WSG_W(6) WSG_W(7) WSG_W(8)
+        WSG_W(9) WSG_W(10) WSG_W(11) WSG_W(12) WSG_W(13) WSG_W(14) WSG_W(15) WSG_W(16)
+#undef WSG_W
+        default: break;
+    }
+}
+
+template <typename R, int LOGN>
+void launch_fft_n(bool grid, const DevParams& P, cpx<R>* stack, cpx<R>* inter, const cpx<R>* tw, const R* corr,
+                  const R* image, R* dirty, hipStream_t s) {
+    using C = FftCfg<R, LOGN>;
+    const unsigned grid_a = unsigned(P.n_layers) * unsigned(C::N / C::kNLt);
+    const unsigned grid_b = unsigned((P.N + C::kNLr - 1) / C::kNLr);
+    if (grid) {
+        {
+            StageMark mark(s, 2);
+            hipLaunchKernelGGL((k_grid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
+                               (const cpx<R>*)stack, inter, tw, P.N, P.n_layers);
+        }
+        StageMark mark(s, 3);
+        hipLaunchKernelGGL((k_grid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
+                           (const cpx<R>*)inter, tw, corr, dirty, P);
+    } else {
+        {
+            StageMark mark(s, 5);
+            hipLaunchKernelGGL((k_degrid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s, image, corr,
+                               tw, inter, P);
+        }
+        StageMark mark(s, 6);
+        hipLaunchKernelGGL((k_degrid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
+                           (const cpx<R>*)inter, tw, stack, P.N, P.n_layers);
+    }
+}
+
+template <typename R>
+void launch_fft(bool grid, int log2n, const DevParams& P, cpx<R>* stack, cpx<R>* inter, const cpx<R>* tw,
+                const R* corr, const R* image, R* dirty, hipStream_t s) {
+    switch (log2n) {
+#define WSG_N(n) \
+    case n: launch_fft_n<R, n>(grid, P, stack, inter, tw, corr, image, dirty, s); break;
+        WSG_N(6) WSG_N(7) WSG_N(8) WSG_N(9) WSG_N(10) WSG_N(11) WSG_N(12) WSG_N(13)
+#undef WSG_N
+        default: break;
+    }
+}
+
+// a: the input array, b: the output array; with M = 0 the visibility-sized
+// one of them may be null (nothing is read from or written to it).
+int check_call(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* a, bool a_empty_ok,
+               const void* b, bool b_empty_ok, void* ws, size_t ws_bytes, Layout* L) {
+    if (!plan) return fail(WSG_EINVAL, "null plan");
+    if (prec != WSG_F32 && prec != WSG_F64) return fail(WSG_EINVAL, "prec must be WSG_F32 or WSG_F64");
+    if (M < 0 || M > 0x7fffffffLL) return fail(WSG_EINVAL, "M must be in [0, 2^31)");
+    if (M > 0 && !uvw) return fail(WSG_EINVAL, "null uvw pointer");
+    if (!a && (M > 0 || !a_empty_ok)) return fail(WSG_EINVAL, "null visibility/image pointer");
+    if (!b && (M > 0 || !b_empty_ok)) return fail(WSG_EINVAL, "null output pointer");
+    if (!ws) return fail(WSG_EINVAL, "null workspace");
+    *L = layout_of(plan, prec, M);
+    if (ws_bytes < L->total)
+        return fail(WSG_EWORKSPACE, "workspace too small: need " + std::to_string(L->total) + " bytes");
+    int dev = -1;
+    WSG_HIP(hipGetDevice(&dev));
+    if (dev != plan->device) return fail(WSG_EINVAL, "plan was created on another device");
+    return WSG_OK;
+}
+
+template <typename R>
+int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const void* in, void* out, void* ws,
+        const Layout& L, hipStream_t s) {
+    const DevParams P = dev_params(plan);
+    char* w = static_cast<char*>(ws);
+    auto* stack = reinterpret_cast<cpx<R>*>(w + L.stack);
+    auto* inter = reinterpret_cast<cpx<R>*>(w + L.inter);
+    auto* rec = reinterpret_cast<Rec<R>*>(w + L.rec);
+    auto* count = reinterpret_cast<uint32_t*>(w + L.count);
+    auto* start = reinterpret_cast<uint32_t*>(w + L.start);
+    auto* cursor = reinterpret_cast<uint32_t*>(w + L.cursor);
+    auto* bsums = reinterpret_cast<uint32_t*>(w + L.bsums);
+    auto* skipped = reinterpret_cast<uint32_t*>(w + L.skipped);
+    const bool f64 = sizeof(R) == 8;
+    const R* coef = f64 ? reinterpret_cast<const R*>(plan->poly64) : reinterpret_cast<const R*>(plan->poly32);
+    const R* corr = f64 ? reinterpret_cast<const R*>(plan->corr64) : reinterpret_cast<const R*>(plan->corr32);
+    const cpx<R>* tw = f64 ? reinterpret_cast<const cpx<R>*>(plan->tw64) : reinterpret_cast<const cpx<R>*>(plan->tw32);
+
+    {
+        StageMark mark(s, grid ? 0 : 4);
+        fill<uint32_t>(count, size_t(L.nbins), 0u, s);
+        fill<uint32_t>(cursor, size_t(L.nbins), 0u, s);
+        fill<uint32_t>(skipped, 1, 0u, s);
+        const unsigned vblocks = unsigned((M + 255) / 256);
+        if (M > 0)
+            hipLaunchKernelGGL(k_bin_count, dim3(vblocks), dim3(256), 0, s, uvw, (long long)M, P, count, skipped);
+        scan(count, start, bsums, L.nbins, s);
+        if (M > 0) {
+            if (grid)
+                hipLaunchKernelGGL((k_bin_scatter<R, true>), dim3(vblocks), dim3(256), 0, s, uvw,
+                                   static_cast<const cpx<R>*>(in), (long long)M, P, (const uint32_t*)start, cursor,
+                                   rec);
+            else
+                hipLaunchKernelGGL((k_bin_scatter<R, false>), dim3(vblocks), dim3(256), 0, s, uvw,
+                                   (const cpx<R>*)nullptr, (long long)M, P, (const uint32_t*)start, cursor, rec);
+        }
+    }
+    if (grid) {
+        {
+            StageMark mark(s, 1);
+            launch_tiles<R>(true, P.W, L.nbins, rec, start, P, coef, stack, nullptr, s);
+        }
+        launch_fft<R>(true, plan->log2_np, P, stack, inter, tw, corr, nullptr, static_cast<R*>(out), s);
+    } else {
+        launch_fft<R>(false, plan->log2_np, P, stack, inter, tw, corr, static_cast<const R*>(in), nullptr, s);
+        StageMark mark(s, 7);
+        fill<R>(static_cast<R*>(out), size_t(2 * M), R(0), s);
+        if (M > 0) launch_tiles<R>(false, P.W, L.nbins, rec, start, P, coef, stack, static_cast<R*>(out), s);
+    }
+    WSG_HIP(hipGetLastError());
+    return WSG_OK;
+}
+
+template <typename T>
+int upload(T** dst, const T* src, size_t n) {
+    WSG_HIP(hipMalloc(reinterpret_cast<void**>(dst), n * sizeof(T)));
+    WSG_HIP(hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return WSG_OK;
+}
+
+int build_tables(wsg_plan* p) {
+    const PlanParams& pp = p->pp;
+    const KernelDesign& kd = p->kd;
+    const int N = pp.N, Np = pp.Nprime;
+    std::vector<double> poly64(kd.poly);
+    std::vector<float> poly32(poly64.begin(), poly64.end());
+    int rc;
+    if ((rc = upload(&p->poly64, poly64.data(), poly64.size()))) return rc;
+    if ((rc = upload(&p->poly32, poly32.data(), poly32.size()))) return rc;
+    std::vector<cpx<double>> tw64(Np);
+    std::vector<cpx<float>> tw32(Np);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < Np; ++k) {
+        double a = two_pi * double(k) / double(Np);
+        tw64[k] = {std::cos(a), std::sin(a)};
+        tw32[k] = {float(tw64[k].x), float(tw64[k].y)};
+    }
+    if ((rc = upload(&p->tw64, tw64.data(), tw64.size()))) return rc;
+    if ((rc = upload(&p->tw32, tw32.data(), tw32.size()))) return rc;
+
+    std::vector<double> hx(N);
+    for (int i = 0; i < N; ++i) hx[i] = kd.h_at(double(i - N / 2) / double(Np));
+    double *d_hx = nullptr, *d_c = nullptr, *d_nu = nullptr, *d_wn = nullptr;
+    if ((rc = upload(&d_hx, hx.data(), hx.size()))) return rc;
+    if ((rc = upload(&d_c, kd.c_nodes.data(), kd.c_nodes.size()))) return rc;
+    if ((rc = upload(&d_nu, kd.nun.data(), kd.nun.size()))) return rc;
+    if ((rc = upload(&d_wn, kd.wn.data(), kd.wn.size()))) return rc;
+    WSG_HIP(hipMalloc(reinterpret_cast<void**>(&p->corr64), size_t(N) * N * sizeof(double)));
+    WSG_HIP(hipMalloc(reinterpret_cast<void**>(&p->corr32), size_t(N) * N * sizeof(float)));
+    DevParams P = dev_params(p);
+    hipLaunchKernelGGL(k_corr_map, dim3((N + 255) / 256, N), dim3(256), 0, 0, (const double*)d_hx,
+                       (const double*)d_c, (const double*)d_nu, (const double*)d_wn, int(kd.nun.size()), P,
+                       p->corr64, p->corr32);
+    WSG_HIP(hipGetLastError());
+    WSG_HIP(hipDeviceSynchronize());
+    WSG_HIP(hipFree(d_hx));
+    WSG_HIP(hipFree(d_c));
+    WSG_HIP(hipFree(d_nu));
+    WSG_HIP(hipFree(d_wn));
+    return WSG_OK;
+}
+
+void free_tables(wsg_plan* p) {
+    void* ptrs[] = {p->poly64, p->poly32, p->corr64, p->corr32, p->tw64, p->tw32};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* grid_last_error(void) { return g_err.c_str(); }
+
+void wsg_stage_timing(int enable) { g_timing = enable != 0; }
+
+int wsg_stage_times(double* ms, int* launches, int n) {
+    std::vector<double> acc(WSG_NSTAGES, 0.0);
+    std::vector<int> cnt(WSG_NSTAGES, 0);
+    int rc = WSG_OK;
+    for (const StageEvent& e : g_events) {
+        float t = 0.f;
+        if (rc == WSG_OK) {
+            hipError_t err = hipEventSynchronize(e.b);
+            if (err == hipSuccess) err = hipEventElapsedTime(&t, e.a, e.b);
+            if (err != hipSuccess) rc = fail(WSG_EHIP, std::string("stage timing: ") + hipGetErrorString(err));
+        }
+        acc[e.stage] += t;
+        cnt[e.stage] += 1;
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    g_events.clear();
+    if (rc != WSG_OK) return rc;
+    for (int i = 0; i < n && i < WSG_NSTAGES; ++i) {
+        if (ms) ms[i] = acc[i];
+        if (launches) launches[i] = cnt[i];
+    }
+    return WSG_NSTAGES;
+}
+
+int wsg_plan_params(int N, double L, int W, double x0, double wmax, int* Nprime, int* t_lo, int* t_hi,
+                    double* n0, double* n_scale) {
+    PlanParams pp;
+    std::string e = make_plan_params(N, L, W, x0, wmax, &pp);
+    if (!e.empty()) return fail(WSG_EINVAL, e);
+    if (Nprime) *Nprime = pp.Nprime;
+    if (t_lo) *t_lo = pp.t_lo;
+    if (t_hi) *t_hi = pp.t_hi;
+    if (n0) *n0 = pp.n0;
+    if (n_scale) *n_scale = pp.n_scale;
+    return WSG_OK;
+}
+
+int wsg_design_eval(int W, double x0, int n_nu, const double* nu, double* c_out, int n_x, const double* x,
+                    double* h_out, double* E_out) {
+    try {
+        if (n_nu < 0 || n_x < 0) return fail(WSG_EINVAL, "negative count");
+        if ((n_nu > 0 && (!nu || !c_out)) || (n_x > 0 && (!x || !h_out))) return fail(WSG_EINVAL, "null pointer");
+        KernelDesign kd = design_kernel(W, x0);
+        for (int k = 0; k < n_nu; ++k) {
+            if (!(nu[k] >= -0.5 && nu[k] <= 0.5)) return fail(WSG_EINVAL, "nu outside [-1/2, 1/2]");
+            for (int a = 0; a < W; ++a) c_out[size_t(k) * W + a] = kd.c_poly(a, nu[k]);
+        }
+        for (int k = 0; k < n_x; ++k) {
+            if (!(std::fabs(x[k]) <= 0.5)) return fail(WSG_EINVAL, "|x| > 1/2");
+            h_out[k] = kd.h_at(x[k]);
+        }
+        if (E_out) *E_out = kd.E;
+        return WSG_OK;
+    } catch (const std::exception& e) {
+        return fail(WSG_EINVAL, e.what());
+    }
+}
+
+wsg_plan* grid_create(int N, double L, int W, double x0, double wmax) {
+    wsg_plan* p = nullptr;
+    try {
+        PlanParams pp;
+        std::string e = make_plan_params(N, L, W, x0, wmax, &pp);
+        if (!e.empty()) {
+            fail(WSG_EINVAL, e);
+            return nullptr;
+        }
+        const int Np = pp.Nprime;
+        if (Np < 64 || Np > 8192 || (Np & (Np - 1))) {
+            fail(WSG_EINVAL, "N / (2 x0) must be a power of two in [64, 8192]");
+            return nullptr;
+        }
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess) {
+            fail(WSG_EHIP, "no HIP device");
+            return nullptr;
+        }
+        p = new wsg_plan();
+        p->pp = pp;
+        p->device = dev;
+        int lg = 0;
+        while ((1 << lg) < Np) ++lg;
+        p->log2_np = lg;
+        p->nbr = Np / kTileR;
+        p->nbs = Np / kTileS;
+        p->nbt = (pp.n_layers() + kTileT - 1) / kTileT;
+        if ((long long)p->nbr * p->nbs * p->nbt > kMaxBins) {
+            fail(WSG_EINVAL, "too many tiles: reduce N / (2 x0) or wmax");
+            delete p;
+            return nullptr;
+        }
+        p->kd = design_kernel(W, x0);
+        if (build_tables(p) != WSG_OK) {
+            free_tables(p);
+            delete p;
+            return nullptr;
+        }
+        return p;
+    } catch (const std::exception& ex) {
+        fail(WSG_ENOMEM, ex.what());
+        if (p) {
+            free_tables(p);
+            delete p;
+        }
+        return nullptr;
+    }
+}
+
+void grid_destroy(wsg_plan* plan) {
+    if (!plan) return;
+    free_tables(plan);
+    delete plan;
+}
+
+int grid_plan_info(const wsg_plan* plan, int* Nprime, int* t_lo, int* n_layers, double* n0, double* n_scale,
+                   double* E) {
+    if (!plan) return fail(WSG_EINVAL, "null plan");
+    if (Nprime) *Nprime = plan->pp.Nprime;
+    if (t_lo) *t_lo = plan->pp.t_lo;
+    if (n_layers) *n_layers = plan->pp.n_layers();
+    if (n0) *n0 = plan->pp.n0;
+    if (n_scale) *n_scale = plan->pp.n_scale;
+    if (E) *E = plan->kd.E;
+    return WSG_OK;
+}
+
+size_t grid_workspace_bytes(const wsg_plan* plan, int prec, int64_t M) {
+    if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL) return 0;
+    return layout_of(plan, prec, M).total;
+}
+
+int grid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* vis, void* dirty,
+                      void* ws, size_t ws_bytes, void* stream) {
+    Layout L;
+    int rc = check_call(plan, prec, M, uvw, vis, true, dirty, false, ws, ws_bytes, &L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return prec == WSG_F32 ? run<float>(plan, true, M, uvw, vis, dirty, ws, L, s)
+                           : run<double>(plan, true, M, uvw, vis, dirty, ws, L, s);
+}
+
+int degrid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* image, void* vis,
+                        void* ws, size_t ws_bytes, void* stream) {
+    Layout L;
+    int rc = check_call(plan, prec, M, uvw, image, false, vis, true, ws, ws_bytes, &L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return prec == WSG_F32 ? run<float>(plan, false, M, uvw, image, vis, ws, L, s)
+                           : run<double>(plan, false, M, uvw, image, vis, ws, L, s);
+}
+
+int64_t grid_skipped(const wsg_plan* plan, const void* ws, void* stream) {
+    if (!plan || !ws) return fail(WSG_EINVAL, "null plan or workspace");
+    uint32_t n = 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    WSG_HIP(hipMemcpyAsync(&n, ws, sizeof(n), hipMemcpyDeviceToHost, s));   // counter at offset 0
+    WSG_HIP(hipStreamSynchronize(s));
+    return int64_t(n);
+}
+
+}  // extern "C"

@@ -1,0 +1,245 @@
+"""Thin Python binding of the wsgrid C-ABI (include/wsgrid.h).
+
+Argument marshalling only: every step of gridding and degridding runs in the
+HIP library ``libwsgrid.so``.  PyTorch supplies device memory and the stream.
+The functions carry the C names; ``Plan`` wraps them for tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwsgrid.so")
+HEADER = os.path.join(HERE, "..", "include", "wsgrid.h")
+
+WSG_F32, WSG_F64 = 0, 1
+WSG_OK, WSG_EINVAL, WSG_EWORKSPACE, WSG_ENOMEM, WSG_EHIP = 0, -1, -2, -3, -4
+
+_lib = None
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+
+_SIGNATURES = {
+    "grid_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
+    "grid_destroy": (None, [ctypes.c_void_p]),
+    "grid_plan_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, _c_int_p, _c_int_p, _c_double_p, _c_double_p,
+                                      _c_double_p]),
+    "grid_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]),
+    "grid_visibilities": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                         ctypes.c_void_p]),
+    "degrid_visibilities": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                           ctypes.c_void_p]),
+    "grid_skipped": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "grid_last_error": (ctypes.c_char_p, []),
+    "wsg_design_eval": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_double_p, _c_double_p,
+                                       ctypes.c_int, _c_double_p, _c_double_p, _c_double_p]),
+    "wsg_stage_timing": (None, [ctypes.c_int]),
+    "wsg_stage_times": (ctypes.c_int, [_c_double_p, _c_int_p, ctypes.c_int]),
+    "wsg_plan_params": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, _c_int_p, _c_int_p, _c_int_p, _c_double_p, _c_double_p]),
+}
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/wsgrid.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)) - {"defined"})
+
+
+def lib() -> ctypes.CDLL:
+    """Load libwsgrid.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or python paper_2101_11172_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _err(rc: int, what: str):
+    if rc != WSG_OK:
+        raise RuntimeError(f"{what} failed ({rc}): {lib().grid_last_error().decode()}")
+
+
+# ---- the C entry points, by name -------------------------------------------
+
+def grid_create(N: int, L: float, W: int, x0: float, wmax: float) -> int:
+    p = lib().grid_create(N, L, W, x0, wmax)
+    if not p:
+        raise RuntimeError(f"grid_create failed: {lib().grid_last_error().decode()}")
+    return p
+
+
+def grid_destroy(plan: int) -> None:
+    lib().grid_destroy(plan)
+
+
+def grid_plan_info(plan: int) -> dict:
+    Np, tlo, nl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    n0, ns, E = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _err(lib().grid_plan_info(plan, Np, tlo, nl, n0, ns, E), "grid_plan_info")
+    return dict(Nprime=Np.value, t_lo=tlo.value, n_layers=nl.value, n0=n0.value, n_scale=ns.value, E=E.value)
+
+
+def grid_workspace_bytes(plan: int, prec: int, M: int) -> int:
+    n = lib().grid_workspace_bytes(plan, prec, M)
+    if n == 0:
+        raise RuntimeError("grid_workspace_bytes: bad argument")
+    return n
+
+
+def grid_visibilities(plan: int, prec: int, M: int, uvw_ptr: int, vis_ptr: int, dirty_ptr: int,
+                      ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _err(lib().grid_visibilities(plan, prec, M, uvw_ptr, vis_ptr, dirty_ptr, ws_ptr, ws_bytes, stream),
+         "grid_visibilities")
+
+
+def degrid_visibilities(plan: int, prec: int, M: int, uvw_ptr: int, image_ptr: int, vis_ptr: int,
+                        ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _err(lib().degrid_visibilities(plan, prec, M, uvw_ptr, image_ptr, vis_ptr, ws_ptr, ws_bytes, stream),
+         "degrid_visibilities")
+
+
+def grid_skipped(plan: int, ws_ptr: int, stream: int) -> int:
+    n = lib().grid_skipped(plan, ws_ptr, stream)
+    if n < 0:
+        raise RuntimeError(f"grid_skipped failed: {lib().grid_last_error().decode()}")
+    return int(n)
+
+
+def grid_last_error() -> str:
+    return lib().grid_last_error().decode()
+
+
+def wsg_design_eval(W: int, x0: float, nu, x):
+    """Library's own design (host only): c [len(nu), W] from the device polynomials, h(x), E."""
+    import numpy as np
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    c = np.zeros((nu.size, W))
+    h = np.zeros(x.size)
+    E = ctypes.c_double()
+    dp = lambda a: a.ctypes.data_as(_c_double_p)
+    _err(lib().wsg_design_eval(W, x0, nu.size, dp(nu), dp(c), x.size, dp(x), dp(h), E), "wsg_design_eval")
+    return c, h, E.value
+
+
+def wsg_plan_params(N: int, L: float, W: int, x0: float, wmax: float) -> dict:
+    Np, tlo, thi = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    n0, ns = ctypes.c_double(), ctypes.c_double()
+    _err(lib().wsg_plan_params(N, L, W, x0, wmax, Np, tlo, thi, n0, ns), "wsg_plan_params")
+    return dict(Nprime=Np.value, t_lo=tlo.value, t_hi=thi.value, n0=n0.value, n_scale=ns.value)
+
+
+STAGES = ("grid_bin", "grid_tiles", "grid_fft_v", "grid_fft_u", "degrid_bin", "degrid_fft_p", "degrid_fft_q",
+          "degrid_tiles")
+
+
+def wsg_stage_timing(enable: bool) -> None:
+    lib().wsg_stage_timing(1 if enable else 0)
+
+
+def wsg_stage_times() -> dict:
+    """{stage name: (total ms, launches)} since the last call; waits for the events."""
+    n = len(STAGES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int * n)()
+    rc = lib().wsg_stage_times(ms, cnt, n)
+    if rc < 0:
+        raise RuntimeError(f"wsg_stage_times failed: {grid_last_error()}")
+    return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+# ---- tensor convenience ------------------------------------------------------
+
+_PREC = {torch.complex64: WSG_F32, torch.complex128: WSG_F64, torch.float32: WSG_F32, torch.float64: WSG_F64}
+
+
+class Plan:
+    """Improved W-stacking plan on one HIP device (see include/wsgrid.h)."""
+
+    def __init__(self, N: int, L: float, W: int, x0: float, wmax: float, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("wsgrid needs a HIP device")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            self._p = grid_create(N, L, W, x0, wmax)
+        self.N, self.L, self.W, self.x0, self.wmax = N, L, W, x0, wmax
+        self.info = grid_plan_info(self._p)
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "_p", None):
+            grid_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, prec: int, M: int) -> torch.Tensor:
+        need = grid_workspace_bytes(self._p, prec, M)
+        ws = self._ws.get(prec)
+        if ws is None or ws.numel() < need:
+            self._ws.pop(prec, None)
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws[prec] = ws
+        return ws
+
+    def _check_uvw(self, uvw: torch.Tensor) -> int:
+        if uvw.dtype != torch.float64 or uvw.device != self.device or uvw.dim() != 2 or uvw.shape[1] != 3 \
+                or not uvw.is_contiguous():
+            raise ValueError("uvw must be a contiguous float64 [M, 3] tensor on the plan's device")
+        return uvw.shape[0]
+
+    def grid(self, uvw: torch.Tensor, vis: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        M = self._check_uvw(uvw)
+        if vis.dtype not in (torch.complex64, torch.complex128) or vis.shape != (M,) or not vis.is_contiguous() \
+                or vis.device != self.device:
+            raise ValueError("vis must be a contiguous complex64/complex128 [M] tensor on the plan's device")
+        prec = _PREC[vis.dtype]
+        rdt = torch.float32 if prec == WSG_F32 else torch.float64
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=rdt, device=self.device)
+        elif out.dtype != rdt or out.shape != (self.N, self.N) or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or shape")
+        ws = self.workspace(prec, M)
+        grid_visibilities(self._p, prec, M, uvw.data_ptr(), vis.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                          ws.numel(), torch.cuda.current_stream(self.device).cuda_stream)
+        return out
+
+    def degrid(self, uvw: torch.Tensor, image: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        M = self._check_uvw(uvw)
+        if image.dtype not in (torch.float32, torch.float64) or image.shape != (self.N, self.N) \
+                or not image.is_contiguous() or image.device != self.device:
+            raise ValueError("image must be a contiguous float32/float64 [N, N] tensor on the plan's device")
+        prec = _PREC[image.dtype]
+        cdt = torch.complex64 if prec == WSG_F32 else torch.complex128
+        if out is None:
+            out = torch.empty(M, dtype=cdt, device=self.device)
+        elif out.dtype != cdt or out.shape != (M,) or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or shape")
+        ws = self.workspace(prec, M)
+        degrid_visibilities(self._p, prec, M, uvw.data_ptr(), image.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                            ws.numel(), torch.cuda.current_stream(self.device).cuda_stream)
+        return out
+
+    def skipped(self, prec: int) -> int:
+        ws = self._ws[prec]
+        return grid_skipped(self._p, ws.data_ptr(), torch.cuda.current_stream(self.device).cuda_stream)

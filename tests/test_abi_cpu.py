@@ -1,0 +1,61 @@
+"""Host-side checks of the C-ABI library (no GPU compute).
+
+* the library loads and exports every function include/wsgrid.h declares;
+* its planner gives the oracle planner's values;
+* its own least-misfit design applies the same h(x) g(x, nu) as the oracle's
+  (only this product enters the operators, see oracle.kernel_design);
+* argument validation.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.kernel_design import least_misfit
+from oracle.plan import make_plan
+from paper_2101_11172_amd import wsgrid as wg
+
+
+def test_exports_every_declared_function():
+    names = wg.header_functions()
+    assert "grid_create" in names and "degrid_visibilities" in names
+    for n in names:
+        assert hasattr(wg.lib(), n), n
+
+
+@pytest.mark.parametrize("args", [(256, 0.2, 7, 0.25, 300.0), (2048, 0.4, 7, 0.25, 511.3),
+                                  (2048, 0.4, 4, 0.5, 511.3), (64, 0.3, 5, 0.2, 10.0)])
+def test_planner_matches_oracle(args):
+    got = wg.wsg_plan_params(*args)
+    p = make_plan(*args)
+    assert got["Nprime"] == p.Nprime and got["t_lo"] == p.t_lo and got["t_hi"] == p.t_hi
+    assert got["n0"] == p.n0 and got["n_scale"] == p.n_scale
+
+
+@pytest.mark.parametrize("W,x0,tol", [(7, 0.25, 1e-12), (4, 0.25, 1e-12), (5, 0.2, 1e-12), (9, 0.25, 1e-11),
+                                      (4, 0.5, 1e-8)])
+def test_design_applies_same_product_as_oracle(W, x0, tol):
+    nu = np.linspace(-0.5, 0.5, 41)
+    x = np.linspace(-x0, x0, 33)
+    c, h, E = wg.wsg_design_eval(W, x0, nu, x)
+    lm = least_misfit(W, x0)
+    s = np.arange(W) - (W - 1) / 2
+    g = np.einsum("js,jsi->ji", c, np.exp(2j * np.pi * (s[None, :, None] - nu[:, None, None]) * x[None, None, :]))
+    assert np.max(np.abs(h[None, :] * g - lm.hg(x, nu))) <= tol
+    assert abs(E - lm.E) <= 1e-6 * lm.E
+
+
+def test_design_rejects_bad_arguments():
+    with pytest.raises(RuntimeError):
+        wg.wsg_design_eval(0, 0.25, [0.0], [0.0])
+    with pytest.raises(RuntimeError):
+        wg.wsg_design_eval(7, 0.25, [0.7], [0.0])
+    with pytest.raises(RuntimeError):
+        wg.wsg_plan_params(255, 0.2, 7, 0.25, 1.0)
+    with pytest.raises(RuntimeError):
+        wg.wsg_plan_params(256, 0.2, 7, 0.3, 1.0)
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-device error path")
+def test_create_without_device_fails_cleanly():
+    assert not wg.lib().grid_create(256, 0.2, 7, 0.25, 300.0)
+    assert "device" in wg.grid_last_error()
