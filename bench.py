@@ -143,15 +143,46 @@ def cpu_baseline(w: dict, n_sample: int) -> dict:
     }
 
 
+def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int) -> dict:
+    tab = {}
+    for name, (ms, n) in stages.items():
+        if n == 0:
+            continue
+        per = ms / n
+        nbytes = stage_bytes(name, M, N, Np, nl, f64)
+        tab[name] = {"ms": per, "launches": n, "alg_bytes": nbytes, "alg_GBps": nbytes / (per * 1e-3) / 1e9}
+    return tab
+
+
+def timed(step, steps: int):
+    """Run `steps` steps with per-stage event timing; returns (ms per step, stage times)."""
+    import torch
+
+    from paper_2101_11172_amd import wsgrid
+
+    torch.cuda.synchronize()
+    wsgrid.wsg_stage_times()            # clear
+    wsgrid.wsg_stage_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wsgrid.wsg_stage_timing(False)
+    return (t1 - t0) * 1e3 / steps, wsgrid.wsg_stage_times()
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dumps", type=int, default=4960, help="time samples (M = 2016 x dumps)")
-    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=3, help="0 skips the FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=10000)
+    ap.add_argument("--copy-gb", type=float, default=0.0,
+                    help="first run one device-to-device copy of this many GB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path is built and measured on a single MI355X "
@@ -164,6 +195,14 @@ def main() -> int:
     from paper_2101_11172_amd import inputs, wsgrid
 
     dev = torch.device("cuda", 0)
+    if args.copy_gb > 0:
+        n = int(args.copy_gb * 1e9) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {4 * n} bytes read, {4 * n} bytes written")
+        del src, dst
     log("generating the wide-field workload")
     w = inputs.workload("widefield", n_dumps=args.dumps, vis_dtype=np.complex64)
     N, L, W, x0, wmax = w["N"], w["L"], w["W"], w["x0"], w["wmax"]
@@ -186,62 +225,33 @@ def main() -> int:
         step32()
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{args.warmup} done")
-    wsgrid.wsg_stage_times()            # clear
-    wsgrid.wsg_stage_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step32()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wsgrid.wsg_stage_timing(False)
-    stages32 = wsgrid.wsg_stage_times()
-    ms32 = (t1 - t0) * 1e3 / args.steps
+    ms32, stages32 = timed(step32, args.steps)
     log(f"fp32: {ms32:.3f} ms/step, {M / (ms32 * 1e-3):.4e} vis/s")
     skipped = plan.skipped(wsgrid.WSG_F32)
+    tab32 = stage_table(stages32, False, M, N, Np, nl)
 
-    # FP64 path on the same data
-    uvw64_vis = vis32.to(torch.complex128)
-    img64 = img32.double()
-    out_img64 = torch.empty((N, N), dtype=torch.float64, device=dev)
-    out_vis64 = torch.empty(M, dtype=torch.complex128, device=dev)
+    fp64, acc = None, None
+    if args.fp64_steps > 0:
+        vis64, img64 = vis32.to(torch.complex128), img32.double()
+        out_img64 = torch.empty((N, N), dtype=torch.float64, device=dev)
+        out_vis64 = torch.empty(M, dtype=torch.complex128, device=dev)
 
-    def step64():
-        plan.grid(uvw, uvw64_vis, out=out_img64)
-        plan.degrid(uvw, img64, out=out_vis64)
+        def step64():
+            plan.grid(uvw, vis64, out=out_img64)
+            plan.degrid(uvw, img64, out=out_vis64)
 
-    step64()
-    torch.cuda.synchronize()
-    wsgrid.wsg_stage_times()
-    wsgrid.wsg_stage_timing(True)
-    t0 = time.perf_counter()
-    for i in range(args.fp64_steps):
         step64()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wsgrid.wsg_stage_timing(False)
-    stages64 = wsgrid.wsg_stage_times()
-    ms64 = (t1 - t0) * 1e3 / args.fp64_steps
-    log(f"fp64: {ms64:.3f} ms/step, {M / (ms64 * 1e-3):.4e} vis/s")
+        ms64, stages64 = timed(step64, args.fp64_steps)
+        log(f"fp64: {ms64:.3f} ms/step, {M / (ms64 * 1e-3):.4e} vis/s")
+        fp64 = {"value": M / (ms64 * 1e-3), "ms_per_step": ms64,
+                "stages": stage_table(stages64, True, M, N, Np, nl)}
 
-    def relrms(a, b):
-        return float(torch.linalg.vector_norm(a.double() - b.double()) / torch.linalg.vector_norm(b.double()))
+        def relrms(a, b):
+            return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
-    acc = {"grid": relrms(out_img32, out_img64),
-           "degrid": relrms(out_vis32.to(torch.complex128), out_vis64)}
+        acc = {"grid": relrms(out_img32.double(), out_img64),
+               "degrid": relrms(out_vis32.to(torch.complex128), out_vis64)}
 
-    def stage_table(stages, f64):
-        tab = {}
-        for name, (ms, n) in stages.items():
-            if n == 0:
-                continue
-            per = ms / n
-            nbytes = stage_bytes(name, M, N, Np, nl, f64)
-            tab[name] = {"ms": per, "launches": n, "alg_bytes": nbytes, "alg_GBps": nbytes / (per * 1e-3) / 1e9}
-        return tab
-
-    tab32 = stage_table(stages32, False)
-    tab64 = stage_table(stages64, True)
     dom = max(tab32, key=lambda k: tab32[k]["ms"])
     d = tab32[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -267,15 +277,14 @@ def main() -> int:
                    "N": N, "L": L, "W": W, "x0": x0, "visibilities": M, "w_layers": nl, "fft_size": Np},
         "roofline": roofline,
         "whole_step_alg_GBps": total_alg / (ms32 * 1e-3) / 1e9,
-        "fp64": {"value": M / (ms64 * 1e-3), "ms_per_step": ms64, "stages": tab64},
+        "fp64": fp64,
         "fp32_vs_fp64_rel_rms": acc,
         "stages": tab32,
         "skipped": skipped,
     }
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
-        w64 = dict(w)
-        result["cpu_baseline"] = cpu_baseline(w64, args.cpu_sample)
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
         log(f"cpu oracle: {result['cpu_baseline']['value']:.4e} vis/s")
     print(json.dumps(result), flush=True)
     plan.close()

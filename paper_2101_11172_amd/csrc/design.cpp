@@ -21,7 +21,8 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kNodes = 32;        // Gauss-Legendre nodes in x and in nu
-constexpr int kDegree = 16;       // per-segment polynomial degree in nu
+constexpr int kDegree = 16;       // per-segment polynomial degree in nu, float64 path
+constexpr int kDegreeLo = 10;     // float32 path: fit error <= 1e-10 for W <= 12
 
 void gauss_legendre(int n, double a, double b, std::vector<double>& x, std::vector<double>& w) {
     x.assign(n, 0.0);
@@ -227,6 +228,41 @@ std::vector<double> damped_lstsq(const std::vector<double>& J, const std::vector
     return d;
 }
 
+// Per-segment polynomial in nu of degree Dg: interpolate c at Dg+1 Chebyshev
+// points of [-1/2, 1/2], then convert the Chebyshev series (in t = 2 nu) to
+// monomials in nu.  Returns [W][Dg+1].
+std::vector<double> fit_segments(const KernelDesign& D, int Dg) {
+    const int W = D.W, np = Dg + 1;
+    std::vector<double> out(size_t(W) * np, 0.0), vals(size_t(np) * W);
+    for (int k = 0; k < np; ++k) {
+        double t = std::cos(kPi * (k + 0.5) / np);
+        D.c_exact(0.5 * t, &vals[size_t(k) * W]);
+    }
+    std::vector<double> T(size_t(np) * np, 0.0);      // T_q(t) in monomials
+    T[0] = 1.0;
+    if (np > 1) T[1 * np + 1] = 1.0;
+    for (int q = 2; q < np; ++q)
+        for (int e = 0; e < np; ++e) {
+            double v = -T[(q - 2) * np + e];
+            if (e > 0) v += 2.0 * T[(q - 1) * np + e - 1];
+            T[q * np + e] = v;
+        }
+    for (int a = 0; a < W; ++a) {
+        std::vector<double> cheb(np, 0.0);
+        for (int q = 0; q < np; ++q) {
+            double acc = 0;
+            for (int k = 0; k < np; ++k) acc += vals[size_t(k) * W + a] * std::cos(kPi * q * (k + 0.5) / np);
+            cheb[q] = acc * (q == 0 ? 1.0 : 2.0) / np;
+        }
+        for (int e = 0; e < np; ++e) {
+            double acc = 0;
+            for (int q = e; q < np; ++q) acc += cheb[q] * T[q * np + e];
+            out[size_t(a) * np + e] = acc * std::ldexp(1.0, e);   // t^e = (2 nu)^e
+        }
+    }
+    return out;
+}
+
 }  // namespace
 
 void KernelDesign::c_exact(double nu, double* c) const {
@@ -246,6 +282,13 @@ double KernelDesign::c_poly(int a, double nu) const {
     const double* p = &poly[size_t(a) * (degree + 1)];
     double v = p[degree];
     for (int k = degree - 1; k >= 0; --k) v = v * nu + p[k];
+    return v;
+}
+
+double KernelDesign::c_poly_lo(int a, double nu) const {
+    const double* p = &poly_lo[size_t(a) * (degree_lo + 1)];
+    double v = p[degree_lo];
+    for (int k = degree_lo - 1; k >= 0; --k) v = v * nu + p[k];
     return v;
 }
 
@@ -374,39 +417,10 @@ KernelDesign design_kernel(int W, double x0) {
     for (double& e : h) e /= h0;
     finish(h);
 
-    // Per-segment polynomial in nu: interpolate at degree+1 Chebyshev points of
-    // [-1/2, 1/2], then convert the Chebyshev series (in t = 2 nu) to monomials in nu.
-    const int Dg = kDegree, np = Dg + 1;
-    D.degree = Dg;
-    D.poly.assign(size_t(W) * np, 0.0);
-    std::vector<double> vals(size_t(np) * W);
-    for (int k = 0; k < np; ++k) {
-        double t = std::cos(kPi * (k + 0.5) / np);
-        D.c_exact(0.5 * t, &vals[size_t(k) * W]);
-    }
-    // T_n(t) monomial tables
-    std::vector<double> T(size_t(np) * np, 0.0);
-    T[0] = 1.0;
-    if (np > 1) T[1 * np + 1] = 1.0;
-    for (int q = 2; q < np; ++q)
-        for (int e = 0; e < np; ++e) {
-            double v = -T[(q - 2) * np + e];
-            if (e > 0) v += 2.0 * T[(q - 1) * np + e - 1];
-            T[q * np + e] = v;
-        }
-    for (int a = 0; a < W; ++a) {
-        std::vector<double> cheb(np, 0.0);
-        for (int q = 0; q < np; ++q) {
-            double acc = 0;
-            for (int k = 0; k < np; ++k) acc += vals[size_t(k) * W + a] * std::cos(kPi * q * (k + 0.5) / np);
-            cheb[q] = acc * (q == 0 ? 1.0 : 2.0) / np;
-        }
-        for (int e = 0; e < np; ++e) {
-            double acc = 0;
-            for (int q = e; q < np; ++q) acc += cheb[q] * T[q * np + e];
-            D.poly[size_t(a) * np + e] = acc * std::ldexp(1.0, e);   // t^e = (2 nu)^e
-        }
-    }
+    D.degree = kDegree;
+    D.poly = fit_segments(D, kDegree);
+    D.degree_lo = kDegreeLo;
+    D.poly_lo = fit_segments(D, kDegreeLo);
 
     // E on a finer grid, from the fitted polynomials and the pointwise h.
     std::vector<double> fx, fwx, fn, fwn;

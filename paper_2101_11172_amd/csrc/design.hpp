@@ -17,13 +17,16 @@ struct KernelDesign {
     std::vector<double> h;           // h at xn, scaled so that h(0) = 1
     std::vector<double> A;           // W x W normal matrix for h
     std::vector<double> c_nodes;     // [nun.size()][W] c at the nu nodes
-    int degree = 0;                  // per-segment polynomial degree in nu
+    int degree = 0;                  // per-segment polynomial degree in nu (float64 path)
     std::vector<double> poly;        // [W][degree+1] monomial coefficients in nu
+    int degree_lo = 0;               // lower degree for the float32 path
+    std::vector<double> poly_lo;     // [W][degree_lo+1]
     double E = 0;                    // error bound, evaluated on a finer grid
     int iterations = 0;
 
     void c_exact(double nu, double* c) const;       // normal equations, W values
-    double c_poly(int a, double nu) const;          // fitted polynomial
+    double c_poly(int a, double nu) const;          // fitted polynomial (float64 path)
+    double c_poly_lo(int a, double nu) const;       // fitted polynomial (float32 path)
     double h_at(double x) const;                    // pointwise optimality formula
 };
 

@@ -187,23 +187,45 @@ __global__ void k_bin_scatter(const double* __restrict__ uvw, const cpx<R>* __re
 
 // ------------------------------------------------ 3-D scatter / gather tiles --
 //
-// One block owns one tile of kTileT layers x kTileR u-cells x kTileS v-cells of
-// the stack (layout [t][r][s], s fastest) and takes every contribution that
-// lands in it (owner computes: no global atomics, every tile written once).
-// The visibilities whose support can reach the tile are those binned (by first
-// support index) in this tile or in the previous tile along each axis.
-// Each wave takes a batch of up to 64 records: lane i evaluates record i's
-// 3W kernel weights (Horner in nu, per-segment polynomial) into the wave's LDS
-// scratch, then the wave walks the records that touch the tile, with its lanes
-// over the (a_r, a_s) support pairs and a loop over the layers a_t.
+// One 256-thread block owns one tile of kTileT layers x kTileR u-cells x
+// kTileS v-cells of the stack (layout [t][r][s], s fastest).  Thread
+// (rr, ss) = (tid / 16, tid % 16) owns the column of kTileT cells at
+// (r0 + rr, s0 + ss) and keeps them in registers; wave w owns rows
+// rr = 4w .. 4w + 3.  The visibilities whose support can reach the tile are
+// those binned (by first support index) in this tile or the previous one
+// along each axis (8 bins).  They are staged in rounds of kBatch: each thread
+// loads one record, tests it against the tile, and the touching ones are
+// compacted in order into LDS with their weights: C_u and C_v for the W
+// support offsets, and C_w placed at the tile's layer slots (zero elsewhere).
+// Then every wave walks the staged list; lanes inside a record's uv support
+// apply it to (grid) or read it from (degrid) their kTileT cells.  No atomics
+// touch the tile, and each tile is read or written once.
+
+// Kernel polynomial degree in nu per precision (the host fits both).
+template <typename R>
+struct KernelDegree {
+    static constexpr int value = sizeof(R) == 8 ? 16 : 10;
+};
 
 template <typename R, int W>
 struct TileCfg {
-    static constexpr int kWaves = 4;
-    static constexpr int kBatch = (sizeof(R) == 8 && W > 8) ? 32 : 64;
-    static constexpr int kPairs = W * W;
-    static constexpr int kPairIters = (kPairs + 63) / 64;
-    static constexpr int kCells = kTileT * kTileR * kTileS;
+    static constexpr int kDeg = KernelDegree<R>::value;
+    static constexpr int kThreads = 256;
+    static constexpr int kBatch = sizeof(R) == 8 ? 128 : 256;
+    static_assert(kTileR * kTileS == kThreads, "one thread per (r, s) column");
+    static_assert(kTileT == 16, "register slots per thread");
+};
+
+template <typename R, int W>
+struct TileStage {
+    R wuv[TileCfg<R, W>::kBatch][2 * W];     // C(s_a - nu_u), then C(s_a - nu_v)
+    R sh[TileCfg<R, W>::kBatch][kTileT];     // C(s_a - nu_w) at layer slot dt + a
+    R val[TileCfg<R, W>::kBatch][2];
+    int duv[TileCfg<R, W>::kBatch];          // (dr + 128) | (ds + 128) << 16
+    uint32_t idx[TileCfg<R, W>::kBatch];
+    R out[TileCfg<R, W>::kBatch][2];         // degrid: per-record partial sums
+    int wcount[4];
+    int n;
 };
 
 // Signed offset of a support start from the tile origin along a periodic axis.
@@ -214,61 +236,65 @@ __device__ __forceinline__ int wrap_offset(int first, int origin, int Np) {
     return d;
 }
 
+// Stage records [base, min(base + kBatch, end)) that touch the tile.  Must be
+// called by the whole block; ends with the staged list visible to all threads.
 template <typename R, int W>
-struct WaveScratch {
-    R w[TileCfg<R, W>::kBatch][3 * W];
-    R val[TileCfg<R, W>::kBatch][2];
-    int box[TileCfg<R, W>::kBatch][4];     // d_r, d_s, d_t packed bounds, idx
-};
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename R>
-__device__ __forceinline__ R horner(const R* __restrict__ c, int degree, R nu) {
-    R v = c[degree];
-    for (int k = degree - 1; k >= 0; --k) v = v * nu + c[k];
-    return v;
-}
-
-// Load the records of bin range [b0, b1) that touch the tile; returns the
-// ballot of lanes holding a touching record.  Bounds per axis are packed as
-// lo | hi << 8 | (d + 128) << 16 in weight-index space.
-template <typename R, int W>
-__device__ __forceinline__ unsigned long long stage_batch(const Rec<R>* __restrict__ rec, uint32_t i,
-                                                          uint32_t end, int r0, int s0, int t0, int nt_valid,
-                                                          const DevParams& P, const R* __restrict__ coef,
-                                                          WaveScratch<R, W>& ws, int lane, bool gather) {
+__device__ __forceinline__ void stage_round(const Rec<R>* __restrict__ rec, uint32_t base, uint32_t end, int r0,
+                                            int s0, int t0, int nt_valid, const DevParams& P,
+                                            const R* __restrict__ coef, TileStage<R, W>& st) {
+    using Cfg = TileCfg<R, W>;
+    constexpr int D = Cfg::kDeg;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t i = base + uint32_t(tid);
     bool touch = false;
-    if (i < end) {
-        Rec<R> r = rec[i];
+    Rec<R> r;
+    int dr = 0, ds = 0, dt = 0;
+    if (tid < Cfg::kBatch && i < end) {
+        r = rec[i];
         const int ru = int(r.ruv & 0xffffu), rv = int(r.ruv >> 16), rt = int(r.rt);
-        const int dr = wrap_offset(ru, r0, P.Np), ds = wrap_offset(rv, s0, P.Np), dt = rt - t0;
-        const int lor = max(0, -dr), hir = min(W - 1, kTileR - 1 - dr);
-        const int los = max(0, -ds), his = min(W - 1, kTileS - 1 - ds);
-        const int lot = max(0, -dt), hit = min(W - 1, nt_valid - 1 - dt);
-        touch = lor <= hir && los <= his && lot <= hit;
-        if (touch) {
-            const int D = P.degree;
-#pragma unroll
-            for (int a = 0; a < W; ++a) {
-                ws.w[lane][a] = horner(coef + a * (D + 1), D, r.nu[0]);
-                ws.w[lane][W + a] = horner(coef + a * (D + 1), D, r.nu[1]);
-                ws.w[lane][2 * W + a] = horner(coef + a * (D + 1), D, r.nu[2]);
-            }
-            ws.val[lane][0] = r.v[0];
-            ws.val[lane][1] = r.v[1];
-            ws.box[lane][0] = lor | (hir << 8) | ((dr + 128) << 16);
-            ws.box[lane][1] = los | (his << 8) | ((ds + 128) << 16);
-            ws.box[lane][2] = lot | (hit << 8) | ((dt + 128) << 16);
-            ws.box[lane][3] = int(r.idx);
-        }
+        dr = wrap_offset(ru, r0, P.Np);
+        ds = wrap_offset(rv, s0, P.Np);
+        dt = rt - t0;
+        touch = dr + W > 0 && dr < kTileR && ds + W > 0 && ds < kTileS && dt + W > 0 && dt < nt_valid;
     }
-    (void)gather;
-    return __ballot(touch);
+    // order-preserving compaction: wave prefix by ballot, block prefix over 4 waves
+    const unsigned long long m = __ballot(touch);
+    const int wpos = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) st.wcount[wv] = __popcll(m);
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wv; ++w) off += st.wcount[w];
+    if (tid == 0) st.n = st.wcount[0] + st.wcount[1] + st.wcount[2] + st.wcount[3];
+    if (touch) {
+        const int slot = off + wpos;
+#pragma unroll
+        for (int k = 0; k < kTileT; ++k) st.sh[slot][k] = R(0);
+        // the same least-misfit function on every axis: each coefficient read
+        // (an LDS broadcast) feeds the three Horner chains
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const R* c = coef + a * (D + 1);
+            R pu = c[D], pv = c[D], pt = c[D];
+#pragma unroll
+            for (int k = D - 1; k >= 0; --k) {
+                const R ck = c[k];
+                pu = pu * r.nu[0] + ck;
+                pv = pv * r.nu[1] + ck;
+                pt = pt * r.nu[2] + ck;
+            }
+            st.wuv[slot][a] = pu;
+            st.wuv[slot][W + a] = pv;
+            const int k = dt + a;
+            if (k >= 0 && k < kTileT) st.sh[slot][k] = pt;
+        }
+        st.val[slot][0] = r.v[0];
+        st.val[slot][1] = r.v[1];
+        st.duv[slot] = (dr + 128) | ((ds + 128) << 16);
+        st.idx[slot] = r.idx;
+        st.out[slot][0] = R(0);
+        st.out[slot][1] = R(0);
+    }
+    __syncthreads();
 }
 
 template <typename R, int W>
@@ -276,77 +302,55 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
                                                     const uint32_t* __restrict__ start, DevParams P,
                                                     const R* __restrict__ coef_g, cpx<R>* __restrict__ stack) {
     using Cfg = TileCfg<R, W>;
-    __shared__ R tre[Cfg::kCells];
-    __shared__ R tim[Cfg::kCells];
-    __shared__ WaveScratch<R, W> scratch[Cfg::kWaves];
-    __shared__ R coef[W * 24];
+    __shared__ TileStage<R, W> st;
+    __shared__ R coef[W * (Cfg::kDeg + 1)];
 
     const int nblocks = P.nbt * P.nbs * P.nbr;
-    const int tile = xcd_remap(blockIdx.x, nblocks);
+    const int tile = xcd_interleave<4>(blockIdx.x, nblocks);
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0);
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, wv = tid >> 6;
+    const int rr = tid >> 4, ss = tid & 15, row0 = wv * 4;
 
-    for (int i = tid; i < Cfg::kCells; i += 256) {
-        tre[i] = R(0);
-        tim[i] = R(0);
-    }
-    for (int i = tid; i < W * (P.degree + 1); i += 256) coef[i] = coef_g[i];
+    for (int i = tid; i < W * (Cfg::kDeg + 1); i += 256) coef[i] = coef_g[i];
+    R ax[kTileT], ay[kTileT];
+#pragma unroll
+    for (int k = 0; k < kTileT; ++k) ax[k] = ay[k] = R(0);
     __syncthreads();
 
-    WaveScratch<R, W>& ws = scratch[wv];
     const int nbr_prev = (P.nbr > 1) ? 2 : 1, nbs_prev = (P.nbs > 1) ? 2 : 1, nbt_prev = (bt > 0) ? 2 : 1;
     for (int it = 0; it < nbt_prev; ++it)
         for (int is = 0; is < nbs_prev; ++is)
             for (int ir = 0; ir < nbr_prev; ++ir) {
-                const int cbt = bt - it;
-                const int cbs = (bs - is + P.nbs) % P.nbs;
-                const int cbr = (br - ir + P.nbr) % P.nbr;
-                const int bin = (cbt * P.nbs + cbs) * P.nbr + cbr;
+                const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
                 const uint32_t b0 = start[bin], b1 = start[bin + 1];
-                for (uint32_t base = b0 + uint32_t(wv) * Cfg::kBatch; base < b1;
-                     base += uint32_t(Cfg::kWaves) * Cfg::kBatch) {
-                    // every lane takes part in the ballot; lanes past the batch hold no record
-                    const uint32_t ri = lane < Cfg::kBatch ? base + uint32_t(lane) : b1;
-                    unsigned long long mask =
-                        stage_batch<R, W>(rec, ri, b1, r0, s0, t0, nt_valid, P, coef, ws, lane, false);
-                    wave_sync();
-                    while (mask) {
-                        const int q = __ffsll(mask) - 1;
-                        mask &= mask - 1;
-                        const int br_ = ws.box[q][0], bs_ = ws.box[q][1], bt_ = ws.box[q][2];
-                        const int lor = br_ & 255, hir = (br_ >> 8) & 255, dr = (br_ >> 16) - 128;
-                        const int los = bs_ & 255, his = (bs_ >> 8) & 255, ds = (bs_ >> 16) - 128;
-                        const int lot = bt_ & 255, hit = (bt_ >> 8) & 255, dt = (bt_ >> 16) - 128;
-                        const R vx = ws.val[q][0], vy = ws.val[q][1];
+                for (uint32_t base = b0; base < b1; base += Cfg::kBatch) {
+                    stage_round<R, W>(rec, base, b1, r0, s0, t0, nt_valid, P, coef, st);
+                    const int n = st.n;
+                    for (int j = 0; j < n; ++j) {
+                        const int duv = st.duv[j];
+                        const int dr = (duv & 0xffff) - 128, ds = (duv >> 16) - 128;
+                        if (dr + W <= row0 || dr > row0 + 3) continue;     // misses this wave's rows
+                        const int ar = rr - dr, as = ss - ds;
+                        if (ar >= 0 && ar < W && as >= 0 && as < W) {
+                            const R wrs = st.wuv[j][ar] * st.wuv[j][W + as];
+                            const R px = st.val[j][0] * wrs, py = st.val[j][1] * wrs;
 #pragma unroll
-                        for (int pi = 0; pi < Cfg::kPairIters; ++pi) {
-                            const int pr = lane + 64 * pi;
-                            const int ar = pr / W, as = pr - (pr / W) * W;
-                            if (pr < Cfg::kPairs && ar >= lor && ar <= hir && as >= los && as <= his) {
-                                const R wrs = ws.w[q][ar] * ws.w[q][W + as];
-                                const R px = vx * wrs, py = vy * wrs;
-                                const int cell_rs = (dr + ar) * kTileS + (ds + as);
-                                for (int at = lot; at <= hit; ++at) {
-                                    const R wt = ws.w[q][2 * W + at];
-                                    const int cell = (dt + at) * (kTileR * kTileS) + cell_rs;
-                                    atomicAdd(&tre[cell], px * wt);
-                                    atomicAdd(&tim[cell], py * wt);
-                                }
+                            for (int k = 0; k < kTileT; ++k) {
+                                const R wt = st.sh[j][k];
+                                ax[k] += px * wt;
+                                ay[k] += py * wt;
                             }
                         }
                     }
-                    wave_sync();
+                    __syncthreads();
                 }
             }
-    __syncthreads();
-    // write the tile: rows of kTileS cells
-    for (int i = tid; i < nt_valid * kTileR * kTileS; i += 256) {
-        const int ss = i % kTileS, rr = (i / kTileS) % kTileR, tt = i / (kTileR * kTileS);
-        const size_t g = ((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss);
-        stack[g] = cpx<R>{tre[i], tim[i]};
-    }
+    cpx<R>* dst = stack + ((size_t)t0 * P.Np + (r0 + rr)) * P.Np + (s0 + ss);
+#pragma unroll
+    for (int k = 0; k < kTileT; ++k)
+        if (k < nt_valid) dst[(size_t)k * P.Np * P.Np] = cpx<R>{ax[k], ay[k]};
 }
 
 template <typename R, int W>
@@ -355,86 +359,91 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
                                                       const R* __restrict__ coef_g,
                                                       const cpx<R>* __restrict__ stack, R* __restrict__ vis) {
     using Cfg = TileCfg<R, W>;
-    __shared__ R tre[Cfg::kCells];
-    __shared__ R tim[Cfg::kCells];
-    __shared__ WaveScratch<R, W> scratch[Cfg::kWaves];
-    __shared__ R coef[W * 24];
+    __shared__ TileStage<R, W> st;
+    __shared__ R coef[W * (Cfg::kDeg + 1)];
+    __shared__ uint32_t any;
 
     const int nblocks = P.nbt * P.nbs * P.nbr;
-    const int tile = xcd_remap(blockIdx.x, nblocks);
+    const int tile = xcd_interleave<4>(blockIdx.x, nblocks);
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-
-    for (int i = tid; i < nt_valid * kTileR * kTileS; i += 256) {
-        const int ss = i % kTileS, rr = (i / kTileS) % kTileR, tt = i / (kTileR * kTileS);
-        const cpx<R> q = stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)];
-        tre[i] = q.x;
-        tim[i] = q.y;
-    }
-    for (int i = tid; i < W * (P.degree + 1); i += 256) coef[i] = coef_g[i];
-    __syncthreads();
-
-    WaveScratch<R, W>& ws = scratch[wv];
+    const int rr = tid >> 4, ss = tid & 15, row0 = wv * 4;
     const int nbr_prev = (P.nbr > 1) ? 2 : 1, nbs_prev = (P.nbs > 1) ? 2 : 1, nbt_prev = (bt > 0) ? 2 : 1;
+
+    // a tile no visibility can reach is not read at all
+    if (tid == 0) {
+        uint32_t tot = 0;
+        for (int it = 0; it < nbt_prev; ++it)
+            for (int is = 0; is < nbs_prev; ++is)
+                for (int ir = 0; ir < nbr_prev; ++ir) {
+                    const int bin =
+                        ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
+                    tot += start[bin + 1] - start[bin];
+                }
+        any = tot;
+    }
+    for (int i = tid; i < W * (Cfg::kDeg + 1); i += 256) coef[i] = coef_g[i];
+    __syncthreads();
+    if (any == 0) return;
+
+    R qx[kTileT], qy[kTileT];
+    const cpx<R>* src = stack + ((size_t)t0 * P.Np + (r0 + rr)) * P.Np + (s0 + ss);
+#pragma unroll
+    for (int k = 0; k < kTileT; ++k) {
+        const cpx<R> q = k < nt_valid ? src[(size_t)k * P.Np * P.Np] : cpx<R>{R(0), R(0)};
+        qx[k] = q.x;
+        qy[k] = q.y;
+    }
+
     for (int it = 0; it < nbt_prev; ++it)
         for (int is = 0; is < nbs_prev; ++is)
             for (int ir = 0; ir < nbr_prev; ++ir) {
-                const int cbt = bt - it;
-                const int cbs = (bs - is + P.nbs) % P.nbs;
-                const int cbr = (br - ir + P.nbr) % P.nbr;
-                const int bin = (cbt * P.nbs + cbs) * P.nbr + cbr;
+                const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
                 const uint32_t b0 = start[bin], b1 = start[bin + 1];
-                for (uint32_t base = b0 + uint32_t(wv) * Cfg::kBatch; base < b1;
-                     base += uint32_t(Cfg::kWaves) * Cfg::kBatch) {
-                    // every lane takes part in the ballot; lanes past the batch hold no record
-                    const uint32_t ri = lane < Cfg::kBatch ? base + uint32_t(lane) : b1;
-                    unsigned long long mask =
-                        stage_batch<R, W>(rec, ri, b1, r0, s0, t0, nt_valid, P, coef, ws, lane, true);
-                    wave_sync();
-                    while (mask) {
-                        const int q = __ffsll(mask) - 1;
-                        mask &= mask - 1;
-                        const int br_ = ws.box[q][0], bs_ = ws.box[q][1], bt_ = ws.box[q][2];
-                        const int lor = br_ & 255, hir = (br_ >> 8) & 255, dr = (br_ >> 16) - 128;
-                        const int los = bs_ & 255, his = (bs_ >> 8) & 255, ds = (bs_ >> 16) - 128;
-                        const int lot = bt_ & 255, hit = (bt_ >> 8) & 255, dt = (bt_ >> 16) - 128;
-                        R ax = R(0), ay = R(0);
+                for (uint32_t base = b0; base < b1; base += Cfg::kBatch) {
+                    stage_round<R, W>(rec, base, b1, r0, s0, t0, nt_valid, P, coef, st);
+                    const int n = st.n;
+                    for (int j = 0; j < n; ++j) {
+                        const int duv = st.duv[j];
+                        const int dr = (duv & 0xffff) - 128, ds = (duv >> 16) - 128;
+                        if (dr + W <= row0 || dr > row0 + 3) continue;     // misses this wave's rows
+                        const int ar = rr - dr, as = ss - ds;
+                        R px = R(0), py = R(0);
+                        if (ar >= 0 && ar < W && as >= 0 && as < W) {
+                            R sx = R(0), sy = R(0);
 #pragma unroll
-                        for (int pi = 0; pi < Cfg::kPairIters; ++pi) {
-                            const int pr = lane + 64 * pi;
-                            const int ar = pr / W, as = pr - (pr / W) * W;
-                            if (pr < Cfg::kPairs && ar >= lor && ar <= hir && as >= los && as <= his) {
-                                const int cell_rs = (dr + ar) * kTileS + (ds + as);
-                                R sx = R(0), sy = R(0);
-                                for (int at = lot; at <= hit; ++at) {
-                                    const R wt = ws.w[q][2 * W + at];
-                                    const int cell = (dt + at) * (kTileR * kTileS) + cell_rs;
-                                    sx += tre[cell] * wt;
-                                    sy += tim[cell] * wt;
-                                }
-                                const R wrs = ws.w[q][ar] * ws.w[q][W + as];
-                                ax += sx * wrs;
-                                ay += sy * wrs;
+                            for (int k = 0; k < kTileT; ++k) {
+                                const R wt = st.sh[j][k];
+                                sx += qx[k] * wt;
+                                sy += qy[k] * wt;
                             }
+                            const R wrs = st.wuv[j][ar] * st.wuv[j][W + as];
+                            px = sx * wrs;
+                            py = sy * wrs;
                         }
-#pragma unroll
-                        for (int o = 32; o > 0; o >>= 1) {
-                            ax += __shfl_xor(ax, o, 64);
-                            ay += __shfl_xor(ay, o, 64);
-                        }
-                        if (lane == 0) {
-                            const R px = ws.val[q][0], py = ws.val[q][1];
-                            R ox = ax * px - ay * py, oy = ax * py + ay * px;
-                            const uint32_t idx = uint32_t(ws.box[q][3]);
-                            if (idx & 0x80000000u) oy = -oy;
-                            const size_t k = idx & 0x7fffffffu;
-                            atomicAdd(&vis[2 * k], ox);
-                            atomicAdd(&vis[2 * k + 1], oy);
+                        px = wave_sum_lane63(px);
+                        py = wave_sum_lane63(py);
+                        if (lane == 63) {
+                            atomicAdd(&st.out[j][0], px);
+                            atomicAdd(&st.out[j][1], py);
                         }
                     }
-                    wave_sync();
+                    __syncthreads();
+                    // one global update per record and tile: phase exp(-i 2 pi w (n0 - 1)),
+                    // conjugate for a folded visibility
+                    if (tid < n) {
+                        const R sx = st.out[tid][0], sy = st.out[tid][1];
+                        const R cx = st.val[tid][0], cy = st.val[tid][1];
+                        R ox = sx * cx - sy * cy, oy = sx * cy + sy * cx;
+                        const uint32_t idx = st.idx[tid];
+                        if (idx & 0x80000000u) oy = -oy;
+                        const size_t k = idx & 0x7fffffffu;
+                        atomicAdd(&vis[2 * k], ox);
+                        atomicAdd(&vis[2 * k + 1], oy);
+                    }
+                    __syncthreads();
                 }
             }
 }

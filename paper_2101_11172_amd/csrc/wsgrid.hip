@@ -123,7 +123,6 @@ DevParams dev_params(const wsg_plan* p) {
     P.nbr = p->nbr;
     P.nbs = p->nbs;
     P.nbt = p->nbt;
-    P.degree = p->kd.degree;
     P.umul = p->pp.l_max / p->pp.x0;
     P.nscale = p->pp.n_scale;
     P.z0 = p->pp.x0;
@@ -294,8 +293,10 @@ int build_tables(wsg_plan* p) {
     const PlanParams& pp = p->pp;
     const KernelDesign& kd = p->kd;
     const int N = pp.N, Np = pp.Nprime;
+    if (kd.degree != KernelDegree<double>::value || kd.degree_lo != KernelDegree<float>::value)
+        return fail(WSG_EINVAL, "kernel polynomial degree mismatch between design and device code");
     std::vector<double> poly64(kd.poly);
-    std::vector<float> poly32(poly64.begin(), poly64.end());
+    std::vector<float> poly32(kd.poly_lo.begin(), kd.poly_lo.end());
     int rc;
     if ((rc = upload(&p->poly64, poly64.data(), poly64.size()))) return rc;
     if ((rc = upload(&p->poly32, poly32.data(), poly32.size()))) return rc;

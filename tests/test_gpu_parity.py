@@ -14,7 +14,11 @@ Tolerances (relative RMS over the whole output, plus a max-abs check):
   layer sum is correspondingly small and set by FP32 cancellation; the FP32
   dirty map is therefore compared before that exact elementwise scaling
   (both maps divided by the oracle's correction), the correction itself being
-  checked by the FP64 comparison.
+  checked by the FP64 comparison.  Degridding at x0 = 1/2 feeds f h_x h_y h_z,
+  whose entries span six orders of magnitude, into FP32 transforms: their
+  absolute error is ~2^-24 |f h h h|, so the FP32 bound there is
+  max(1e-6, 2^-24 rms(h_x h_y h_z)) (1.8e-2 for W = 4; 2e-7 at x0 = 1/4).
+  The method's own error at x0 = 1/2 is E = 0.07.
 Cases span several 16 x 16 x 16 tiles and ragged tails in every dimension.
 """
 import numpy as np
@@ -101,7 +105,8 @@ def test_grid_degrid_match_oracle(case):
         if x0 == 0.5 and prec == 32:
             g, ref_g_cmp = g / corr, ref_g / corr
             assert rel(g, ref_g_cmp) <= tol, (prec, "grid before correction", rel(g, ref_g_cmp))
-            assert rel(d, ref_d) <= tol, (prec, "degrid", rel(d, ref_d))
+            tol_d = max(tol, 2.0 ** -24 * float(np.sqrt(np.mean(corr ** 2))))
+            assert rel(d, ref_d) <= tol_d, (prec, "degrid", rel(d, ref_d), tol_d)
             continue
         assert rel(g, ref_g) <= tol, (prec, "grid", rel(g, ref_g))
         assert rel(d, ref_d) <= tol, (prec, "degrid", rel(d, ref_d))
