@@ -185,21 +185,73 @@ __global__ void k_bin_scatter(const double* __restrict__ uvw, const cpx<R>* __re
     rec[pos] = r;
 }
 
+// Second-level sort: inside each bin, order the records by their first support
+// index within the tile (a 12-bit key: layer, u, v offsets), so that records
+// with the same support box are adjacent (they form long runs on Earth-rotation
+// tracks).  One block per bin: LDS histogram of the 4096 keys, exclusive scan,
+// scatter to `out` in key order (order within one key is arbitrary).
+template <typename R>
+__global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict__ in, Rec<R>* __restrict__ out,
+                                                        const uint32_t* __restrict__ start, DevParams P) {
+    __shared__ uint32_t hist[kTileT * kTileR * kTileS];
+    __shared__ uint32_t sh[16];
+    const int bin = blockIdx.x;
+    const uint32_t b0 = start[bin], b1 = start[bin + 1];
+    if (b1 - b0 <= 1) {
+        if (b1 > b0 && threadIdx.x == 0) out[b0] = in[b0];
+        return;
+    }
+    const int br = bin % P.nbr, bs = (bin / P.nbr) % P.nbs, bt = bin / (P.nbr * P.nbs);
+    const int tid = threadIdx.x;
+    constexpr int NK = kTileT * kTileR * kTileS;
+    for (int i = tid; i < NK; i += 256) hist[i] = 0u;
+    __syncthreads();
+    auto key_of = [&](const Rec<R>& r) {
+        const int ru = int(r.ruv & 0xffffu) - br * kTileR, rv = int(r.ruv >> 16) - bs * kTileS;
+        const int rt = int(r.rt) - bt * kTileT;
+        return (rt * kTileR + ru) * kTileS + rv;
+    };
+    for (uint32_t i = b0 + tid; i < b1; i += 256) atomicAdd(&hist[key_of(in[i])], 1u);
+    __syncthreads();
+    // exclusive scan: 16 consecutive keys per thread
+    uint32_t v[NK / 256], sum = 0;
+#pragma unroll
+    for (int k = 0; k < NK / 256; ++k) {
+        v[k] = hist[tid * (NK / 256) + k];
+        sum += v[k];
+    }
+    uint32_t total;
+    uint32_t off = block_exclusive_scan(sum, sh, total);
+#pragma unroll
+    for (int k = 0; k < NK / 256; ++k) {
+        hist[tid * (NK / 256) + k] = off;
+        off += v[k];
+    }
+    __syncthreads();
+    for (uint32_t i = b0 + tid; i < b1; i += 256) {
+        const Rec<R> r = in[i];
+        out[b0 + atomicAdd(&hist[key_of(r)], 1u)] = r;
+    }
+}
+
 // ------------------------------------------------ 3-D scatter / gather tiles --
 //
 // One 256-thread block owns one tile of kTileT layers x kTileR u-cells x
-// kTileS v-cells of the stack (layout [t][r][s], s fastest).  Thread
-// (rr, ss) = (tid / 16, tid % 16) owns the column of kTileT cells at
-// (r0 + rr, s0 + ss) and keeps them in registers; wave w owns rows
-// rr = 4w .. 4w + 3.  The visibilities whose support can reach the tile are
-// those binned (by first support index) in this tile or the previous one
-// along each axis (8 bins).  They are staged in rounds of kBatch: each thread
-// loads one record, tests it against the tile, and the touching ones are
-// compacted in order into LDS with their weights: C_u and C_v for the W
-// support offsets, and C_w placed at the tile's layer slots (zero elsewhere).
-// Then every wave walks the staged list; lanes inside a record's uv support
-// apply it to (grid) or read it from (degrid) their kTileT cells.  No atomics
-// touch the tile, and each tile is read or written once.
+// kTileS v-cells of the stack (layout [t][r][s], s fastest), held in LDS.  The
+// visibilities whose support can reach the tile are those binned (by first
+// support index) in this tile or the previous one along each axis (8 bins);
+// each bin is sorted by first support index, so records with the same support
+// box are adjacent.  Records are staged in rounds of kBatch: each thread loads
+// one, tests it against the tile, and the touching ones are compacted in order
+// into LDS with their kernel weights.  The staged list is cut into 4
+// contiguous chunks, one per wave; a wave walks its chunk with its lanes over
+// the W x W (u, v) support pairs and W layer registers per pair:
+//   scatter: contributions of a run of equal supports accumulate in registers
+//            and go into the LDS tile (atomic adds) once per run;
+//   gather:  the run's cells are read from the LDS tile once and contracted
+//            with each record's weights; the wave sum (DPP) is the record's
+//            part from this tile.
+// Each tile is read or written to HBM once.
 
 // Kernel polynomial degree in nu per precision (the host fits both).
 template <typename R>
@@ -210,23 +262,38 @@ struct KernelDegree {
 template <typename R, int W>
 struct TileCfg {
     static constexpr int kDeg = KernelDegree<R>::value;
-    static constexpr int kThreads = 256;
-    static constexpr int kBatch = sizeof(R) == 8 ? 128 : 256;
-    static_assert(kTileR * kTileS == kThreads, "one thread per (r, s) column");
-    static_assert(kTileT == 16, "register slots per thread");
+    static constexpr int kBatch = 128;
+    static constexpr int kPairs = W * W;
+    static constexpr int kPI = (kPairs + 63) / 64;     // support pairs per lane
+    static constexpr int kCells = kTileT * kTileR * kTileS;
 };
 
 template <typename R, int W>
 struct TileStage {
+    // words: C(s_a - nu_w) for a < W, then the value (2), then the packed
+    // offsets (dr + 128) | (ds + 128) << 8 | (dt + 128) << 16
+    R words[TileCfg<R, W>::kBatch][W + 3];
     R wuv[TileCfg<R, W>::kBatch][2 * W];     // C(s_a - nu_u), then C(s_a - nu_v)
-    R sh[TileCfg<R, W>::kBatch][kTileT];     // C(s_a - nu_w) at layer slot dt + a
-    R val[TileCfg<R, W>::kBatch][2];
-    int duv[TileCfg<R, W>::kBatch];          // (dr + 128) | (ds + 128) << 16
     uint32_t idx[TileCfg<R, W>::kBatch];
-    R out[TileCfg<R, W>::kBatch][2];         // degrid: per-record partial sums
+    R out[TileCfg<R, W>::kBatch][2];         // gather: the record's sum over this tile
     int wcount[4];
     int n;
 };
+
+__device__ __forceinline__ float bits_to_word(int v, float) { return __int_as_float(v); }
+__device__ __forceinline__ double bits_to_word(int v, double) { return __hiloint2double(0, v); }
+
+// value of `v` in lane l, as a wave-uniform (scalar) value
+__device__ __forceinline__ float lane_val(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_val(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int lane_bits(float v, int l) { return __builtin_amdgcn_readlane(__float_as_int(v), l); }
+__device__ __forceinline__ int lane_bits(double v, int l) { return __builtin_amdgcn_readlane(__double2loint(v), l); }
 
 // Signed offset of a support start from the tile origin along a periodic axis.
 __device__ __forceinline__ int wrap_offset(int first, int origin, int Np) {
@@ -267,8 +334,6 @@ __device__ __forceinline__ void stage_round(const Rec<R>* __restrict__ rec, uint
     if (tid == 0) st.n = st.wcount[0] + st.wcount[1] + st.wcount[2] + st.wcount[3];
     if (touch) {
         const int slot = off + wpos;
-#pragma unroll
-        for (int k = 0; k < kTileT; ++k) st.sh[slot][k] = R(0);
         // the same least-misfit function on every axis: each coefficient read
         // (an LDS broadcast) feeds the three Horner chains
 #pragma unroll
@@ -284,24 +349,33 @@ __device__ __forceinline__ void stage_round(const Rec<R>* __restrict__ rec, uint
             }
             st.wuv[slot][a] = pu;
             st.wuv[slot][W + a] = pv;
-            const int k = dt + a;
-            if (k >= 0 && k < kTileT) st.sh[slot][k] = pt;
+            st.words[slot][a] = pt;
         }
-        st.val[slot][0] = r.v[0];
-        st.val[slot][1] = r.v[1];
-        st.duv[slot] = (dr + 128) | ((ds + 128) << 16);
+        st.words[slot][W] = r.v[0];
+        st.words[slot][W + 1] = r.v[1];
+        st.words[slot][W + 2] = bits_to_word((dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16), R(0));
         st.idx[slot] = r.idx;
-        st.out[slot][0] = R(0);
-        st.out[slot][1] = R(0);
     }
     __syncthreads();
 }
+
+// The 8 bins whose visibilities can reach tile (bt, bs, br), in storage order.
+struct BinWalk {
+    int n_t, n_s, n_r;
+    __device__ BinWalk(const DevParams& P, int bt) : n_t(bt > 0 ? 2 : 1), n_s(P.nbs > 1 ? 2 : 1), n_r(P.nbr > 1 ? 2 : 1) {}
+    __device__ int bin(const DevParams& P, int bt, int bs, int br, int it, int is, int ir) const {
+        return ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
+    }
+};
 
 template <typename R, int W>
 __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ rec,
                                                     const uint32_t* __restrict__ start, DevParams P,
                                                     const R* __restrict__ coef_g, cpx<R>* __restrict__ stack) {
     using Cfg = TileCfg<R, W>;
+    constexpr int PI = Cfg::kPI;
+    __shared__ R tre[Cfg::kCells];
+    __shared__ R tim[Cfg::kCells];
     __shared__ TileStage<R, W> st;
     __shared__ R coef[W * (Cfg::kDeg + 1)];
 
@@ -310,47 +384,91 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0);
-    const int tid = threadIdx.x, wv = tid >> 6;
-    const int rr = tid >> 4, ss = tid & 15, row0 = wv * 4;
-
-    for (int i = tid; i < W * (Cfg::kDeg + 1); i += 256) coef[i] = coef_g[i];
-    R ax[kTileT], ay[kTileT];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wl = min(lane, W + 2);
+    int par[PI], pas[PI];
 #pragma unroll
-    for (int k = 0; k < kTileT; ++k) ax[k] = ay[k] = R(0);
+    for (int i = 0; i < PI; ++i) {
+        const int p = min(lane + 64 * i, Cfg::kPairs - 1);
+        par[i] = p / W;
+        pas[i] = p % W;
+    }
+
+    for (int i = tid; i < Cfg::kCells; i += 256) tre[i] = tim[i] = R(0);
+    for (int i = tid; i < W * (Cfg::kDeg + 1); i += 256) coef[i] = coef_g[i];
     __syncthreads();
 
-    const int nbr_prev = (P.nbr > 1) ? 2 : 1, nbs_prev = (P.nbs > 1) ? 2 : 1, nbt_prev = (bt > 0) ? 2 : 1;
-    for (int it = 0; it < nbt_prev; ++it)
-        for (int is = 0; is < nbs_prev; ++is)
-            for (int ir = 0; ir < nbr_prev; ++ir) {
-                const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
+    // add a run's registers into the LDS tile
+    auto flush = [&](int d, const R (&ax)[PI][W], const R (&ay)[PI][W]) {
+        const int dr = (d & 255) - 128, ds = ((d >> 8) & 255) - 128, dt = ((d >> 16) & 255) - 128;
+#pragma unroll
+        for (int i = 0; i < PI; ++i) {
+            const int rr = dr + par[i], ss = ds + pas[i];
+            if (lane + 64 * i < Cfg::kPairs && rr >= 0 && rr < kTileR && ss >= 0 && ss < kTileS) {
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    const int tt = dt + a;
+                    if (tt >= 0 && tt < nt_valid) {
+                        const int cell = (tt * kTileR + rr) * kTileS + ss;
+                        atomicAdd(&tre[cell], ax[i][a]);
+                        atomicAdd(&tim[cell], ay[i][a]);
+                    }
+                }
+            }
+        }
+    };
+
+    const BinWalk walk(P, bt);
+    for (int it = 0; it < walk.n_t; ++it)
+        for (int is = 0; is < walk.n_s; ++is)
+            for (int ir = 0; ir < walk.n_r; ++ir) {
+                const int bin = walk.bin(P, bt, bs, br, it, is, ir);
                 const uint32_t b0 = start[bin], b1 = start[bin + 1];
                 for (uint32_t base = b0; base < b1; base += Cfg::kBatch) {
                     stage_round<R, W>(rec, base, b1, r0, s0, t0, nt_valid, P, coef, st);
                     const int n = st.n;
-                    for (int j = 0; j < n; ++j) {
-                        const int duv = st.duv[j];
-                        const int dr = (duv & 0xffff) - 128, ds = (duv >> 16) - 128;
-                        if (dr + W <= row0 || dr > row0 + 3) continue;     // misses this wave's rows
-                        const int ar = rr - dr, as = ss - ds;
-                        if (ar >= 0 && ar < W && as >= 0 && as < W) {
-                            const R wrs = st.wuv[j][ar] * st.wuv[j][W + as];
-                            const R px = st.val[j][0] * wrs, py = st.val[j][1] * wrs;
+                    const int j0 = (n * wv) >> 2, j1 = (n * (wv + 1)) >> 2;
+                    R ax[PI][W], ay[PI][W];
 #pragma unroll
-                            for (int k = 0; k < kTileT; ++k) {
-                                const R wt = st.sh[j][k];
-                                ax[k] += px * wt;
-                                ay[k] += py * wt;
+                    for (int i = 0; i < PI; ++i)
+#pragma unroll
+                        for (int a = 0; a < W; ++a) ax[i][a] = ay[i][a] = R(0);
+                    int prev = -1;
+                    for (int j = j0; j < j1; ++j) {
+                        const R word = st.words[j][wl];                    // one word per lane
+                        const int d = lane_bits(word, W + 2);
+                        if (d != prev) {                                   // a new support box
+                            if (prev != -1) flush(prev, ax, ay);
+#pragma unroll
+                            for (int i = 0; i < PI; ++i)
+#pragma unroll
+                                for (int a = 0; a < W; ++a) ax[i][a] = ay[i][a] = R(0);
+                            prev = d;
+                        }
+                        const R vx = lane_val(word, W), vy = lane_val(word, W + 1);
+                        R wt[W];
+#pragma unroll
+                        for (int a = 0; a < W; ++a) wt[a] = lane_val(word, a);
+#pragma unroll
+                        for (int i = 0; i < PI; ++i) {
+                            const R f = st.wuv[j][par[i]] * st.wuv[j][W + pas[i]];
+                            const R fx = vx * f, fy = vy * f;
+#pragma unroll
+                            for (int a = 0; a < W; ++a) {
+                                ax[i][a] += fx * wt[a];
+                                ay[i][a] += fy * wt[a];
                             }
                         }
                     }
+                    if (prev != -1) flush(prev, ax, ay);
                     __syncthreads();
                 }
             }
-    cpx<R>* dst = stack + ((size_t)t0 * P.Np + (r0 + rr)) * P.Np + (s0 + ss);
-#pragma unroll
-    for (int k = 0; k < kTileT; ++k)
-        if (k < nt_valid) dst[(size_t)k * P.Np * P.Np] = cpx<R>{ax[k], ay[k]};
+    // write the tile: rows of kTileS cells
+    for (int i = tid; i < nt_valid * kTileR * kTileS; i += 256) {
+        const int ss = i % kTileS, rr = (i / kTileS) % kTileR, tt = i / (kTileR * kTileS);
+        stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)] = cpx<R>{tre[i], tim[i]};
+    }
 }
 
 template <typename R, int W>
@@ -359,6 +477,9 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
                                                       const R* __restrict__ coef_g,
                                                       const cpx<R>* __restrict__ stack, R* __restrict__ vis) {
     using Cfg = TileCfg<R, W>;
+    constexpr int PI = Cfg::kPI;
+    __shared__ R tre[Cfg::kCells];
+    __shared__ R tim[Cfg::kCells];
     __shared__ TileStage<R, W> st;
     __shared__ R coef[W * (Cfg::kDeg + 1)];
     __shared__ uint32_t any;
@@ -369,17 +490,16 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int rr = tid >> 4, ss = tid & 15, row0 = wv * 4;
-    const int nbr_prev = (P.nbr > 1) ? 2 : 1, nbs_prev = (P.nbs > 1) ? 2 : 1, nbt_prev = (bt > 0) ? 2 : 1;
+    const int wl = min(lane, W + 2);
+    const BinWalk walk(P, bt);
 
     // a tile no visibility can reach is not read at all
     if (tid == 0) {
         uint32_t tot = 0;
-        for (int it = 0; it < nbt_prev; ++it)
-            for (int is = 0; is < nbs_prev; ++is)
-                for (int ir = 0; ir < nbr_prev; ++ir) {
-                    const int bin =
-                        ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
+        for (int it = 0; it < walk.n_t; ++it)
+            for (int is = 0; is < walk.n_s; ++is)
+                for (int ir = 0; ir < walk.n_r; ++ir) {
+                    const int bin = walk.bin(P, bt, bs, br, it, is, ir);
                     tot += start[bin + 1] - start[bin];
                 }
         any = tot;
@@ -387,47 +507,80 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     for (int i = tid; i < W * (Cfg::kDeg + 1); i += 256) coef[i] = coef_g[i];
     __syncthreads();
     if (any == 0) return;
-
-    R qx[kTileT], qy[kTileT];
-    const cpx<R>* src = stack + ((size_t)t0 * P.Np + (r0 + rr)) * P.Np + (s0 + ss);
-#pragma unroll
-    for (int k = 0; k < kTileT; ++k) {
-        const cpx<R> q = k < nt_valid ? src[(size_t)k * P.Np * P.Np] : cpx<R>{R(0), R(0)};
-        qx[k] = q.x;
-        qy[k] = q.y;
+    for (int i = tid; i < nt_valid * kTileR * kTileS; i += 256) {
+        const int ss = i % kTileS, rr = (i / kTileS) % kTileR, tt = i / (kTileR * kTileS);
+        const cpx<R> q = stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)];
+        tre[i] = q.x;
+        tim[i] = q.y;
     }
+    int par[PI], pas[PI];
+#pragma unroll
+    for (int i = 0; i < PI; ++i) {
+        const int p = min(lane + 64 * i, Cfg::kPairs - 1);
+        par[i] = p / W;
+        pas[i] = p % W;
+    }
+    __syncthreads();
 
-    for (int it = 0; it < nbt_prev; ++it)
-        for (int is = 0; is < nbs_prev; ++is)
-            for (int ir = 0; ir < nbr_prev; ++ir) {
-                const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
+    for (int it = 0; it < walk.n_t; ++it)
+        for (int is = 0; is < walk.n_s; ++is)
+            for (int ir = 0; ir < walk.n_r; ++ir) {
+                const int bin = walk.bin(P, bt, bs, br, it, is, ir);
                 const uint32_t b0 = start[bin], b1 = start[bin + 1];
                 for (uint32_t base = b0; base < b1; base += Cfg::kBatch) {
                     stage_round<R, W>(rec, base, b1, r0, s0, t0, nt_valid, P, coef, st);
                     const int n = st.n;
-                    for (int j = 0; j < n; ++j) {
-                        const int duv = st.duv[j];
-                        const int dr = (duv & 0xffff) - 128, ds = (duv >> 16) - 128;
-                        if (dr + W <= row0 || dr > row0 + 3) continue;     // misses this wave's rows
-                        const int ar = rr - dr, as = ss - ds;
-                        R px = R(0), py = R(0);
-                        if (ar >= 0 && ar < W && as >= 0 && as < W) {
-                            R sx = R(0), sy = R(0);
+                    const int j0 = (n * wv) >> 2, j1 = (n * (wv + 1)) >> 2;
+                    R qx[PI][W], qy[PI][W];
+                    int prev = -1;
+                    for (int j = j0; j < j1; ++j) {
+                        const R word = st.words[j][wl];                    // one word per lane
+                        const int d = lane_bits(word, W + 2);
+                        if (d != prev) {                                   // a new support box: read its cells
+                            const int dr = (d & 255) - 128, ds = ((d >> 8) & 255) - 128;
+                            const int dt = ((d >> 16) & 255) - 128;
 #pragma unroll
-                            for (int k = 0; k < kTileT; ++k) {
-                                const R wt = st.sh[j][k];
-                                sx += qx[k] * wt;
-                                sy += qy[k] * wt;
+                            for (int i = 0; i < PI; ++i) {
+                                const int rr = dr + par[i], ss = ds + pas[i];
+                                const bool ok = lane + 64 * i < Cfg::kPairs && rr >= 0 && rr < kTileR && ss >= 0 &&
+                                                ss < kTileS;
+#pragma unroll
+                                for (int a = 0; a < W; ++a) {
+                                    const int tt = dt + a;
+                                    const bool in = ok && tt >= 0 && tt < nt_valid;
+                                    const int cell = in ? (tt * kTileR + rr) * kTileS + ss : 0;
+                                    qx[i][a] = in ? tre[cell] : R(0);
+                                    qy[i][a] = in ? tim[cell] : R(0);
+                                }
                             }
-                            const R wrs = st.wuv[j][ar] * st.wuv[j][W + as];
-                            px = sx * wrs;
-                            py = sy * wrs;
+                            prev = d;
+                        }
+                        R wt[W];
+#pragma unroll
+                        for (int a = 0; a < W; ++a) wt[a] = lane_val(word, a);
+                        R px = R(0), py = R(0);
+#pragma unroll
+                        for (int i = 0; i < PI; ++i) {
+                            R sx0 = R(0), sy0 = R(0), sx1 = R(0), sy1 = R(0);
+#pragma unroll
+                            for (int a = 0; a < W; ++a) {
+                                if (a & 1) {
+                                    sx1 += qx[i][a] * wt[a];
+                                    sy1 += qy[i][a] * wt[a];
+                                } else {
+                                    sx0 += qx[i][a] * wt[a];
+                                    sy0 += qy[i][a] * wt[a];
+                                }
+                            }
+                            const R f = st.wuv[j][par[i]] * st.wuv[j][W + pas[i]];
+                            px += (sx0 + sx1) * f;
+                            py += (sy0 + sy1) * f;
                         }
                         px = wave_sum_lane63(px);
                         py = wave_sum_lane63(py);
                         if (lane == 63) {
-                            atomicAdd(&st.out[j][0], px);
-                            atomicAdd(&st.out[j][1], py);
+                            st.out[j][0] = px;
+                            st.out[j][1] = py;
                         }
                     }
                     __syncthreads();
@@ -435,7 +588,7 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
                     // conjugate for a folded visibility
                     if (tid < n) {
                         const R sx = st.out[tid][0], sy = st.out[tid][1];
-                        const R cx = st.val[tid][0], cy = st.val[tid][1];
+                        const R cx = st.words[tid][W], cy = st.words[tid][W + 1];
                         R ox = sx * cx - sy * cy, oy = sx * cy + sy * cx;
                         const uint32_t idx = st.idx[tid];
                         if (idx & 0x80000000u) oy = -oy;

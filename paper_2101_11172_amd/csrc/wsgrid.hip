@@ -86,7 +86,7 @@ struct wsg_plan {
 namespace {
 
 struct Layout {
-    size_t stack, inter, rec, count, start, cursor, bsums, skipped, total;
+    size_t stack, inter, rec, rec2, count, start, cursor, bsums, skipped, total;
     int nbins, nscan;
 };
 
@@ -109,6 +109,7 @@ Layout layout_of(const wsg_plan* p, int prec, int64_t M) {
     L.stack = off;   off += al256(nl * Np * Np * cs);
     L.inter = off;   off += al256(nl * N * Np * cs);
     L.rec = off;     off += al256(size_t(M) * rs);
+    L.rec2 = off;    off += al256(size_t(M) * rs);
     L.total = off;
     return L;
 }
@@ -236,7 +237,8 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
     char* w = static_cast<char*>(ws);
     auto* stack = reinterpret_cast<cpx<R>*>(w + L.stack);
     auto* inter = reinterpret_cast<cpx<R>*>(w + L.inter);
-    auto* rec = reinterpret_cast<Rec<R>*>(w + L.rec);
+    auto* rec_bin = reinterpret_cast<Rec<R>*>(w + L.rec2);   // binned, unordered within a bin
+    auto* rec = reinterpret_cast<Rec<R>*>(w + L.rec);        // binned and sorted within each bin
     auto* count = reinterpret_cast<uint32_t*>(w + L.count);
     auto* start = reinterpret_cast<uint32_t*>(w + L.start);
     auto* cursor = reinterpret_cast<uint32_t*>(w + L.cursor);
@@ -260,10 +262,12 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
             if (grid)
                 hipLaunchKernelGGL((k_bin_scatter<R, true>), dim3(vblocks), dim3(256), 0, s, uvw,
                                    static_cast<const cpx<R>*>(in), (long long)M, P, (const uint32_t*)start, cursor,
-                                   rec);
+                                   rec_bin);
             else
                 hipLaunchKernelGGL((k_bin_scatter<R, false>), dim3(vblocks), dim3(256), 0, s, uvw,
-                                   (const cpx<R>*)nullptr, (long long)M, P, (const uint32_t*)start, cursor, rec);
+                                   (const cpx<R>*)nullptr, (long long)M, P, (const uint32_t*)start, cursor, rec_bin);
+            hipLaunchKernelGGL(k_bin_local_sort<R>, dim3(L.nbins), dim3(256), 0, s, (const Rec<R>*)rec_bin, rec,
+                               (const uint32_t*)start, P);
         }
     }
     if (grid) {
