@@ -185,31 +185,59 @@ __global__ void k_bin_scatter(const double* __restrict__ uvw, const cpx<R>* __re
     rec[pos] = r;
 }
 
-// Second-level sort: inside each bin, order the records by their first support
-// index within the tile (a 12-bit key: layer, u, v offsets), so that records
-// with the same support box are adjacent (they form long runs on Earth-rotation
-// tracks).  One block per bin: LDS histogram of the 4096 keys, exclusive scan,
-// scatter to `out` in key order (order within one key is arbitrary).
+// Second-level sort and touch classes.  With B = 17 - W, a record whose first
+// support index inside its tile is >= B along an axis also reaches the next
+// tile along that axis (W <= 16: never the one after).  Its touch class is the
+// 3-bit set c = (layer >= B) | (u >= B) << 1 | (v >= B) << 2.  A tile reads,
+// from the bin one tile back along the axes of a set m, exactly the records
+// whose class contains m.  Classes are stored in Gray-code order (position q
+// holds class q ^ (q >> 1)): the records a tile needs from one bin are then at
+// most two contiguous ranges, ten over the eight bins.  Inside a class, records
+// are ordered by (layer, u, v) of their first support index, so that records
+// with the same support box are adjacent (long runs along Earth-rotation
+// tracks).
+__device__ __forceinline__ int class_part(int hi, int B) { return hi ? kTileT - B : B; }
+__device__ __forceinline__ int class_position(int c) { return c ^ (c >> 1) ^ (c >> 2); }   // inverse Gray code
+__device__ __forceinline__ int class_of(int lt, int lr, int ls, int B) {
+    return int(lt >= B) | (int(lr >= B) << 1) | (int(ls >= B) << 2);
+}
+// rank of the first key of class position q (q = 0..8) among the 4096 keys
+__device__ __forceinline__ int class_base(int q, int B) {
+    int b = 0;
+    for (int k = 0; k < q; ++k) {
+        const int c = k ^ (k >> 1);
+        b += class_part(c & 1, B) * class_part(c & 2, B) * class_part(c & 4, B);
+    }
+    return b;
+}
+
+// One block per bin: LDS histogram over the 4096 in-tile positions enumerated
+// in (class position, layer, u, v) order, exclusive scan, scatter to `out`
+// (order among equal keys is arbitrary).  cls[8 bin + q] receives the start of
+// class position q in `out`.
 template <typename R>
 __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict__ in, Rec<R>* __restrict__ out,
-                                                        const uint32_t* __restrict__ start, DevParams P) {
-    __shared__ uint32_t hist[kTileT * kTileR * kTileS];
+                                                        const uint32_t* __restrict__ start,
+                                                        uint32_t* __restrict__ cls, DevParams P) {
+    constexpr int NK = kTileT * kTileR * kTileS;
+    __shared__ uint32_t hist[NK];
     __shared__ uint32_t sh[16];
+    __shared__ int cbase[9];
     const int bin = blockIdx.x;
     const uint32_t b0 = start[bin], b1 = start[bin + 1];
-    if (b1 - b0 <= 1) {
-        if (b1 > b0 && threadIdx.x == 0) out[b0] = in[b0];
-        return;
-    }
+    if (b1 == b0) return;
     const int br = bin % P.nbr, bs = (bin / P.nbr) % P.nbs, bt = bin / (P.nbr * P.nbs);
     const int tid = threadIdx.x;
-    constexpr int NK = kTileT * kTileR * kTileS;
+    const int B = 17 - P.W;
+    if (tid < 9) cbase[tid] = class_base(tid, B);
     for (int i = tid; i < NK; i += 256) hist[i] = 0u;
     __syncthreads();
     auto key_of = [&](const Rec<R>& r) {
-        const int ru = int(r.ruv & 0xffffu) - br * kTileR, rv = int(r.ruv >> 16) - bs * kTileS;
-        const int rt = int(r.rt) - bt * kTileT;
-        return (rt * kTileR + ru) * kTileS + rv;
+        const int lr = int(r.ruv & 0xffffu) - br * kTileR, ls = int(r.ruv >> 16) - bs * kTileS;
+        const int lt = int(r.rt) - bt * kTileT;
+        const int c = class_of(lt, lr, ls, B);
+        const int it = (c & 1) ? lt - B : lt, ir = (c & 2) ? lr - B : lr, is = (c & 4) ? ls - B : ls;
+        return cbase[class_position(c)] + (it * class_part(c & 2, B) + ir) * class_part(c & 4, B) + is;
     };
     for (uint32_t i = b0 + tid; i < b1; i += 256) atomicAdd(&hist[key_of(in[i])], 1u);
     __syncthreads();
@@ -228,6 +256,8 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
         off += v[k];
     }
     __syncthreads();
+    if (tid < 8) cls[8 * size_t(bin) + tid] = b0 + (cbase[tid] < NK ? hist[cbase[tid]] : total);
+    __syncthreads();
     for (uint32_t i = b0 + tid; i < b1; i += 256) {
         const Rec<R> r = in[i];
         out[b0 + atomicAdd(&hist[key_of(r)], 1u)] = r;
@@ -238,20 +268,31 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
 //
 // One 256-thread block owns one tile of kTileT layers x kTileR u-cells x
 // kTileS v-cells of the stack (layout [t][r][s], s fastest), held in LDS.  The
-// visibilities whose support can reach the tile are those binned (by first
-// support index) in this tile or the previous one along each axis (8 bins);
-// each bin is sorted by first support index, so records with the same support
-// box are adjacent.  Records are staged in rounds of kBatch: each thread loads
-// one, tests it against the tile, and the touching ones are compacted in order
-// into LDS with their kernel weights.  The staged list is cut into 4
-// contiguous chunks, one per wave; a wave walks its chunk with its lanes over
-// the W x W (u, v) support pairs and W layer registers per pair:
-//   scatter: contributions of a run of equal supports accumulate in registers
-//            and go into the LDS tile (atomic adds) once per run;
-//   gather:  the run's cells are read from the LDS tile once and contracted
-//            with each record's weights; the wave sum (DPP) is the record's
-//            part from this tile.
-// Each tile is read or written to HBM once.
+// records that reach the tile (from its own bin and the seven bins one tile
+// back, selected by touch class) form a virtual list of at most 64 ranges of
+// the record array.  The list is cut into four contiguous quarters, one per
+// wave; the waves work independently (no block barrier between the tile's
+// set-up and its write-out).  A wave walks its quarter in rounds of kWaveBatch
+// records: each lane stages one record (kernel weights by Horner's rule) into
+// the wave's LDS slots while it already holds its next record in registers.
+//
+// Lanes follow the residue-class scheme of Romein (2012), extended to three
+// axes: lane (x, y) owns, among the W x W x W support cells of a record, the W
+// cells whose u and v indices are congruent to x and y modulo W, one per layer
+// residue a (the cell whose layer is congruent to a).  For a record with
+// support start (dr, ds, dt) that is u-cell dr + ((x - dr) mod W), v-cell
+// ds + ((y - ds) mod W) and layer dt + ((a - dt) mod W).  The staged weights
+// are stored rotated by the support start, so that lane x reads its u weight at
+// position x whatever the record.  When consecutive records move their support
+// by one cell, only the lanes and layer residues whose owned cell changed
+//   scatter: add their register sums into the LDS tile (LDS atomics: the four
+//            waves share the tile) and restart from zero;
+//   gather:  read their new cell from the LDS tile;
+// everything else stays in registers.  Records are sorted by support start
+// inside each touch class, so consecutive supports mostly coincide or move by
+// one cell.  The gather sums each record's W^3 terms over the wave (DPP) and
+// adds the tile's part to the visibility with one global atomic.  Each tile is
+// read or written to HBM once.
 
 // Kernel polynomial degree in nu per precision (the host fits both).
 template <typename R>
@@ -262,28 +303,84 @@ struct KernelDegree {
 template <typename R, int W>
 struct TileCfg {
     static constexpr int kDeg = KernelDegree<R>::value;
-    static constexpr int kBatch = 128;
+    static constexpr int kWaveBatch = sizeof(R) == 8 ? 32 : 64;    // records per wave round
+    static constexpr int kSlots = 4 * kWaveBatch;
     static constexpr int kPairs = W * W;
-    static constexpr int kPI = (kPairs + 63) / 64;     // support pairs per lane
+    static constexpr int kPI = (kPairs + 63) / 64;     // (x, y) residue pairs per lane
     static constexpr int kCells = kTileT * kTileR * kTileS;
 };
 
 template <typename R, int W>
 struct TileStage {
-    // words: C(s_a - nu_w) for a < W, then the value (2), then the packed
-    // offsets (dr + 128) | (ds + 128) << 8 | (dt + 128) << 16
-    R words[TileCfg<R, W>::kBatch][W + 3];
-    R wuv[TileCfg<R, W>::kBatch][2 * W];     // C(s_a - nu_u), then C(s_a - nu_v)
-    uint32_t idx[TileCfg<R, W>::kBatch];
-    R out[TileCfg<R, W>::kBatch][2];         // gather: the record's sum over this tile
-    int wcount[4];
+    // words: layer weights C(s_a - nu_w) rotated (position (a + dt) mod W holds
+    // a), then the value (2), then the packed support start
+    // (dr + 128) | (ds + 128) << 8 | (dt + 128) << 16
+    R words[TileCfg<R, W>::kSlots][W + 3];
+    // u weights rotated by dr, then v weights rotated by ds
+    R wuv[TileCfg<R, W>::kSlots][2 * W];
+};
+
+// The records that reach one tile: ranges [lo[g], lo[g] + off[g+1] - off[g])
+// of the record array, concatenated into a virtual list [0, off[n]).
+struct TileSegs {
+    uint32_t lo[64];
+    uint32_t off[65];
     int n;
 };
+
+// Built by wave 0 (a block barrier must follow).  Lane l handles class position
+// q = l & 7 of the bin one tile back along t, v, u by the bits of l >> 3.
+__device__ __forceinline__ void tile_segments(const uint32_t* __restrict__ start, const uint32_t* __restrict__ cls,
+                                              const DevParams& P, int bt, int bs, int br, TileSegs& sg) {
+    const int lane = threadIdx.x & 63;
+    const int nb = lane >> 3, q = lane & 7;
+    const int it = (nb >> 2) & 1, is = (nb >> 1) & 1, ir = nb & 1;
+    uint32_t lo = 0, hi = 0;
+    bool need = false;
+    if (bt - it >= 0) {
+        const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
+        const uint32_t b0 = start[bin], b1 = start[bin + 1];
+        if (b1 > b0) {
+            lo = cls[8 * size_t(bin) + q];
+            hi = q < 7 ? cls[8 * size_t(bin) + q + 1] : b1;
+            const int c = q ^ (q >> 1);
+            const int m = it | (ir << 1) | (is << 2);
+            need = (c & m) == m;
+        }
+    }
+    const uint32_t len = need ? hi - lo : 0u;
+    const unsigned long long nm = __ballot(need);
+    const bool first = need && !(q > 0 && ((nm >> (lane - 1)) & 1ull));
+    const unsigned long long fm = __ballot(first);
+    uint32_t inc = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (first) {
+        const int g = __popcll(fm & ((1ull << lane) - 1ull));
+        sg.lo[g] = lo;
+        sg.off[g] = inc - len;
+    }
+    if (lane == 63) {
+        const int n = __popcll(fm);
+        sg.n = n;
+        sg.off[n] = inc;
+    }
+}
+
+// record array index of virtual position v
+__device__ __forceinline__ uint32_t seg_index(const TileSegs& sg, int n, uint32_t v) {
+    int g = 0;
+    for (int k = 1; k < n; ++k) g += sg.off[k] <= v ? 1 : 0;
+    return sg.lo[g] + (v - sg.off[g]);
+}
 
 __device__ __forceinline__ float bits_to_word(int v, float) { return __int_as_float(v); }
 __device__ __forceinline__ double bits_to_word(int v, double) { return __hiloint2double(0, v); }
 
-// value of `v` in lane l, as a wave-uniform (scalar) value
+// value of `v` in lane l (l wave-uniform), as a wave-uniform (scalar) value
 __device__ __forceinline__ float lane_val(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
@@ -303,167 +400,200 @@ __device__ __forceinline__ int wrap_offset(int first, int origin, int Np) {
     return d;
 }
 
-// Stage records [base, min(base + kBatch, end)) that touch the tile.  Must be
-// called by the whole block; ends with the staged list visible to all threads.
-template <typename R, int W>
-__device__ __forceinline__ void stage_round(const Rec<R>* __restrict__ rec, uint32_t base, uint32_t end, int r0,
-                                            int s0, int t0, int nt_valid, const DevParams& P,
-                                            const R* __restrict__ coef, TileStage<R, W>& st) {
-    using Cfg = TileCfg<R, W>;
-    constexpr int D = Cfg::kDeg;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const uint32_t i = base + uint32_t(tid);
-    bool touch = false;
-    Rec<R> r;
-    int dr = 0, ds = 0, dt = 0;
-    if (tid < Cfg::kBatch && i < end) {
-        r = rec[i];
-        const int ru = int(r.ruv & 0xffffu), rv = int(r.ruv >> 16), rt = int(r.rt);
-        dr = wrap_offset(ru, r0, P.Np);
-        ds = wrap_offset(rv, s0, P.Np);
-        dt = rt - t0;
-        touch = dr + W > 0 && dr < kTileR && ds + W > 0 && ds < kTileS && dt + W > 0 && dt < nt_valid;
-    }
-    // order-preserving compaction: wave prefix by ballot, block prefix over 4 waves
-    const unsigned long long m = __ballot(touch);
-    const int wpos = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) st.wcount[wv] = __popcll(m);
-    __syncthreads();
-    int off = 0;
-    for (int w = 0; w < wv; ++w) off += st.wcount[w];
-    if (tid == 0) st.n = st.wcount[0] + st.wcount[1] + st.wcount[2] + st.wcount[3];
-    if (touch) {
-        const int slot = off + wpos;
-        // the same least-misfit function on every axis: each coefficient read
-        // (an LDS broadcast) feeds the three Horner chains
-#pragma unroll
-        for (int a = 0; a < W; ++a) {
-            const R* c = coef + a * (D + 1);
-            R pu = c[D], pv = c[D], pt = c[D];
-#pragma unroll
-            for (int k = D - 1; k >= 0; --k) {
-                const R ck = c[k];
-                pu = pu * r.nu[0] + ck;
-                pv = pv * r.nu[1] + ck;
-                pt = pt * r.nu[2] + ck;
-            }
-            st.wuv[slot][a] = pu;
-            st.wuv[slot][W + a] = pv;
-            st.words[slot][a] = pt;
-        }
-        st.words[slot][W] = r.v[0];
-        st.words[slot][W + 1] = r.v[1];
-        st.words[slot][W + 2] = bits_to_word((dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16), R(0));
-        st.idx[slot] = r.idx;
-    }
-    __syncthreads();
+// x mod W in [0, W) for x > -16 W
+template <int W>
+__device__ __forceinline__ int mod_w(int x) {
+    return (x + 16 * W) % W;
 }
 
-// The 8 bins whose visibilities can reach tile (bt, bs, br), in storage order.
-struct BinWalk {
-    int n_t, n_s, n_r;
-    __device__ BinWalk(const DevParams& P, int bt) : n_t(bt > 0 ? 2 : 1), n_s(P.nbs > 1 ? 2 : 1), n_r(P.nbr > 1 ? 2 : 1) {}
-    __device__ int bin(const DevParams& P, int bt, int bs, int br, int it, int is, int ir) const {
-        return ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
+// Orders this wave's LDS accesses around a hand-over between its lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stage one record into slot `slot`: kernel weights on the three axes, rotated
+// by the support start, and the packed support start relative to the tile.
+template <typename R, int W>
+__device__ __forceinline__ void stage_record(const Rec<R>& r, int slot, int r0, int s0, int t0, const DevParams& P,
+                                             const R* __restrict__ coef, TileStage<R, W>& st) {
+    constexpr int D = TileCfg<R, W>::kDeg;
+    const int dr = wrap_offset(int(r.ruv & 0xffffu), r0, P.Np);
+    const int ds = wrap_offset(int(r.ruv >> 16), s0, P.Np);
+    const int dt = int(r.rt) - t0;
+    const int pr = mod_w<W>(dr), ps = mod_w<W>(ds), pt = mod_w<W>(dt);
+    // the same least-misfit function on every axis: each coefficient read
+    // (an LDS broadcast) feeds the three Horner chains
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+        const R* c = coef + a * (D + 1);
+        R hu = c[D], hv = c[D], ht = c[D];
+#pragma unroll
+        for (int k = D - 1; k >= 0; --k) {
+            const R ck = c[k];
+            hu = hu * r.nu[0] + ck;
+            hv = hv * r.nu[1] + ck;
+            ht = ht * r.nu[2] + ck;
+        }
+        int ku = pr + a, kv = ps + a, kt = pt + a;
+        ku -= ku >= W ? W : 0;
+        kv -= kv >= W ? W : 0;
+        kt -= kt >= W ? W : 0;
+        st.wuv[slot][ku] = hu;
+        st.wuv[slot][W + kv] = hv;
+        st.words[slot][kt] = ht;
+    }
+    st.words[slot][W] = r.v[0];
+    st.words[slot][W + 1] = r.v[1];
+    st.words[slot][W + 2] = bits_to_word((dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16), R(0));
+}
+
+__device__ __forceinline__ int tile_of_block(const DevParams& P) {
+    return xcd_interleave<4>(blockIdx.x, P.nbt * P.nbs * P.nbr);
+}
+
+// The lane's residue pairs and its cells for support start (dr, ds).
+template <int W, int PI>
+struct LaneCells {
+    int x[PI], y[PI];
+    bool valid[PI];
+    int r[PI], s[PI];              // owned u- and v-cells (tile-relative)
+    __device__ explicit LaneCells(int lane) {
+#pragma unroll
+        for (int i = 0; i < PI; ++i) {
+            const int p = lane + 64 * i;
+            valid[i] = p < W * W;
+            const int pc = min(p, W * W - 1);
+            x[i] = pc / W;
+            y[i] = pc % W;
+            r[i] = s[i] = -1000;
+        }
     }
 };
 
 template <typename R, int W>
 __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ rec,
-                                                    const uint32_t* __restrict__ start, DevParams P,
+                                                    const uint32_t* __restrict__ start,
+                                                    const uint32_t* __restrict__ cls, DevParams P,
                                                     const R* __restrict__ coef_g, cpx<R>* __restrict__ stack) {
     using Cfg = TileCfg<R, W>;
-    constexpr int PI = Cfg::kPI;
+    constexpr int PI = Cfg::kPI, WB = Cfg::kWaveBatch;
     __shared__ R tre[Cfg::kCells];
     __shared__ R tim[Cfg::kCells];
     __shared__ TileStage<R, W> st;
     __shared__ R coef[W * (Cfg::kDeg + 1)];
+    __shared__ TileSegs sg;
 
-    const int nblocks = P.nbt * P.nbs * P.nbr;
-    const int tile = xcd_interleave<4>(blockIdx.x, nblocks);
+    const int tile = tile_of_block(P);
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0);
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wl = min(lane, W + 2);
-    int par[PI], pas[PI];
-#pragma unroll
-    for (int i = 0; i < PI; ++i) {
-        const int p = min(lane + 64 * i, Cfg::kPairs - 1);
-        par[i] = p / W;
-        pas[i] = p % W;
-    }
 
+    if (tid < 64) tile_segments(start, cls, P, bt, bs, br, sg);
     for (int i = tid; i < Cfg::kCells; i += 256) tre[i] = tim[i] = R(0);
     for (int i = tid; i < W * (Cfg::kDeg + 1); i += 256) coef[i] = coef_g[i];
     __syncthreads();
+    const int nseg = sg.n;
+    const uint32_t total = sg.off[nseg];
+    // this wave's quarter of the list
+    const uint32_t quarter = (total + 3) / 4;
+    const uint32_t q0 = min(total, quarter * uint32_t(wv)), q1 = min(total, q0 + quarter);
 
-    // add a run's registers into the LDS tile
-    auto flush = [&](int d, const R (&ax)[PI][W], const R (&ay)[PI][W]) {
-        const int dr = (d & 255) - 128, ds = ((d >> 8) & 255) - 128, dt = ((d >> 16) & 255) - 128;
+    if (q1 > q0) {
+        LaneCells<W, PI> lc(lane);
+        int ct[W];                               // owned layer per residue (wave-uniform)
+        R ax[PI][W], ay[PI][W];
 #pragma unroll
-        for (int i = 0; i < PI; ++i) {
-            const int rr = dr + par[i], ss = ds + pas[i];
-            if (lane + 64 * i < Cfg::kPairs && rr >= 0 && rr < kTileR && ss >= 0 && ss < kTileS) {
+        for (int a = 0; a < W; ++a) ct[a] = -1000;
 #pragma unroll
-                for (int a = 0; a < W; ++a) {
-                    const int tt = dt + a;
-                    if (tt >= 0 && tt < nt_valid) {
-                        const int cell = (tt * kTileR + rr) * kTileS + ss;
-                        atomicAdd(&tre[cell], ax[i][a]);
-                        atomicAdd(&tim[cell], ay[i][a]);
-                    }
-                }
+        for (int i = 0; i < PI; ++i)
+#pragma unroll
+            for (int a = 0; a < W; ++a) ax[i][a] = ay[i][a] = R(0);
+        auto add_cell = [&](int i, int t, R vx, R vy) {
+            if (lc.valid[i] && unsigned(lc.r[i]) < unsigned(kTileR) && unsigned(lc.s[i]) < unsigned(kTileS) &&
+                unsigned(t) < unsigned(nt_valid)) {
+                const int cell = (t * kTileR + lc.r[i]) * kTileS + lc.s[i];
+                atomicAdd(&tre[cell], vx);
+                atomicAdd(&tim[cell], vy);
             }
-        }
-    };
+        };
 
-    const BinWalk walk(P, bt);
-    for (int it = 0; it < walk.n_t; ++it)
-        for (int is = 0; is < walk.n_s; ++is)
-            for (int ir = 0; ir < walk.n_r; ++ir) {
-                const int bin = walk.bin(P, bt, bs, br, it, is, ir);
-                const uint32_t b0 = start[bin], b1 = start[bin + 1];
-                for (uint32_t base = b0; base < b1; base += Cfg::kBatch) {
-                    stage_round<R, W>(rec, base, b1, r0, s0, t0, nt_valid, P, coef, st);
-                    const int n = st.n;
-                    const int j0 = (n * wv) >> 2, j1 = (n * (wv + 1)) >> 2;
-                    R ax[PI][W], ay[PI][W];
+        const int slot0 = wv * WB;
+        Rec<R> nxt;
+        if (q0 + uint32_t(lane) < q1 && lane < WB) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(lane))];
+        int prev = -1;
+        for (uint32_t base = q0; base < q1; base += WB) {
+            const int n = int(min(uint32_t(WB), q1 - base));
+            if (lane < n) stage_record<R, W>(nxt, slot0 + lane, r0, s0, t0, P, coef, st);
+            wave_sync();
+            const uint32_t vn = base + WB + uint32_t(lane);
+            if (lane < WB && vn < q1) nxt = rec[seg_index(sg, nseg, vn)];
+
+            for (int j = 0; j < n; ++j) {
+                const int slot = slot0 + j;
+                const R word = st.words[slot][wl];                 // one word per lane
+                R fu[PI], fv[PI];
 #pragma unroll
-                    for (int i = 0; i < PI; ++i)
+                for (int i = 0; i < PI; ++i) {
+                    fu[i] = st.wuv[slot][lc.x[i]];
+                    fv[i] = st.wuv[slot][W + lc.y[i]];
+                }
+                const int d = lane_bits(word, W + 2);
+                if (d != prev) {                                   // the support moved
+                    prev = d;
+                    const int dr = (d & 255) - 128, ds = ((d >> 8) & 255) - 128, dt = ((d >> 16) & 255) - 128;
+                    bool mv[PI];
+                    int nr[PI], ns[PI];
 #pragma unroll
-                        for (int a = 0; a < W; ++a) ax[i][a] = ay[i][a] = R(0);
-                    int prev = -1;
-                    for (int j = j0; j < j1; ++j) {
-                        const R word = st.words[j][wl];                    // one word per lane
-                        const int d = lane_bits(word, W + 2);
-                        if (d != prev) {                                   // a new support box
-                            if (prev != -1) flush(prev, ax, ay);
+                    for (int i = 0; i < PI; ++i) {
+                        nr[i] = dr + mod_w<W>(lc.x[i] - dr);
+                        ns[i] = ds + mod_w<W>(lc.y[i] - ds);
+                        mv[i] = nr[i] != lc.r[i] || ns[i] != lc.s[i];
+                    }
 #pragma unroll
-                            for (int i = 0; i < PI; ++i)
-#pragma unroll
-                                for (int a = 0; a < W; ++a) ax[i][a] = ay[i][a] = R(0);
-                            prev = d;
-                        }
-                        const R vx = lane_val(word, W), vy = lane_val(word, W + 1);
-                        R wt[W];
-#pragma unroll
-                        for (int a = 0; a < W; ++a) wt[a] = lane_val(word, a);
+                    for (int a = 0; a < W; ++a) {
+                        const int nt = dt + mod_w<W>(a - dt);
+                        const bool tm = nt != ct[a];
 #pragma unroll
                         for (int i = 0; i < PI; ++i) {
-                            const R f = st.wuv[j][par[i]] * st.wuv[j][W + pas[i]];
-                            const R fx = vx * f, fy = vy * f;
-#pragma unroll
-                            for (int a = 0; a < W; ++a) {
-                                ax[i][a] += fx * wt[a];
-                                ay[i][a] += fy * wt[a];
+                            if (tm || mv[i]) {
+                                add_cell(i, ct[a], ax[i][a], ay[i][a]);
+                                ax[i][a] = ay[i][a] = R(0);
                             }
                         }
+                        ct[a] = nt;
                     }
-                    if (prev != -1) flush(prev, ax, ay);
-                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < PI; ++i) {
+                        lc.r[i] = nr[i];
+                        lc.s[i] = ns[i];
+                    }
+                }
+                const R vx = lane_val(word, W), vy = lane_val(word, W + 1);
+#pragma unroll
+                for (int i = 0; i < PI; ++i) {
+                    const R f = fu[i] * fv[i];
+                    const R fx = vx * f, fy = vy * f;
+#pragma unroll
+                    for (int a = 0; a < W; ++a) {
+                        const R wt = lane_val(word, a);
+                        ax[i][a] += fx * wt;
+                        ay[i][a] += fy * wt;
+                    }
                 }
             }
+            wave_sync();
+        }
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+#pragma unroll
+            for (int i = 0; i < PI; ++i) add_cell(i, ct[a], ax[i][a], ay[i][a]);
+    }
+    __syncthreads();
     // write the tile: rows of kTileS cells
     for (int i = tid; i < nt_valid * kTileR * kTileS; i += 256) {
         const int ss = i % kTileS, rr = (i / kTileS) % kTileR, tt = i / (kTileR * kTileS);
@@ -473,132 +603,148 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
 
 template <typename R, int W>
 __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__ rec,
-                                                      const uint32_t* __restrict__ start, DevParams P,
+                                                      const uint32_t* __restrict__ start,
+                                                      const uint32_t* __restrict__ cls, DevParams P,
                                                       const R* __restrict__ coef_g,
                                                       const cpx<R>* __restrict__ stack, R* __restrict__ vis) {
     using Cfg = TileCfg<R, W>;
-    constexpr int PI = Cfg::kPI;
+    constexpr int PI = Cfg::kPI, WB = Cfg::kWaveBatch;
     __shared__ R tre[Cfg::kCells];
     __shared__ R tim[Cfg::kCells];
     __shared__ TileStage<R, W> st;
     __shared__ R coef[W * (Cfg::kDeg + 1)];
-    __shared__ uint32_t any;
+    __shared__ TileSegs sg;
 
-    const int nblocks = P.nbt * P.nbs * P.nbr;
-    const int tile = xcd_interleave<4>(blockIdx.x, nblocks);
+    const int tile = tile_of_block(P);
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0);
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wl = min(lane, W + 2);
-    const BinWalk walk(P, bt);
 
-    // a tile no visibility can reach is not read at all
-    if (tid == 0) {
-        uint32_t tot = 0;
-        for (int it = 0; it < walk.n_t; ++it)
-            for (int is = 0; is < walk.n_s; ++is)
-                for (int ir = 0; ir < walk.n_r; ++ir) {
-                    const int bin = walk.bin(P, bt, bs, br, it, is, ir);
-                    tot += start[bin + 1] - start[bin];
-                }
-        any = tot;
-    }
+    if (tid < 64) tile_segments(start, cls, P, bt, bs, br, sg);
     for (int i = tid; i < W * (Cfg::kDeg + 1); i += 256) coef[i] = coef_g[i];
     __syncthreads();
-    if (any == 0) return;
+    const int nseg = sg.n;
+    const uint32_t total = sg.off[nseg];
+    if (total == 0) return;     // a tile no visibility reaches is not read at all
+    const uint32_t quarter = (total + 3) / 4;
+    const uint32_t q0 = min(total, quarter * uint32_t(wv)), q1 = min(total, q0 + quarter);
+
+    const int slot0 = wv * WB;
+    Rec<R> nxt;
+    if (q0 + uint32_t(lane) < q1 && lane < WB) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(lane))];
     for (int i = tid; i < nt_valid * kTileR * kTileS; i += 256) {
         const int ss = i % kTileS, rr = (i / kTileS) % kTileR, tt = i / (kTileR * kTileS);
         const cpx<R> q = stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)];
         tre[i] = q.x;
         tim[i] = q.y;
     }
-    int par[PI], pas[PI];
-#pragma unroll
-    for (int i = 0; i < PI; ++i) {
-        const int p = min(lane + 64 * i, Cfg::kPairs - 1);
-        par[i] = p / W;
-        pas[i] = p % W;
-    }
     __syncthreads();
+    if (q1 <= q0) return;
 
-    for (int it = 0; it < walk.n_t; ++it)
-        for (int is = 0; is < walk.n_s; ++is)
-            for (int ir = 0; ir < walk.n_r; ++ir) {
-                const int bin = walk.bin(P, bt, bs, br, it, is, ir);
-                const uint32_t b0 = start[bin], b1 = start[bin + 1];
-                for (uint32_t base = b0; base < b1; base += Cfg::kBatch) {
-                    stage_round<R, W>(rec, base, b1, r0, s0, t0, nt_valid, P, coef, st);
-                    const int n = st.n;
-                    const int j0 = (n * wv) >> 2, j1 = (n * (wv + 1)) >> 2;
-                    R qx[PI][W], qy[PI][W];
-                    int prev = -1;
-                    for (int j = j0; j < j1; ++j) {
-                        const R word = st.words[j][wl];                    // one word per lane
-                        const int d = lane_bits(word, W + 2);
-                        if (d != prev) {                                   // a new support box: read its cells
-                            const int dr = (d & 255) - 128, ds = ((d >> 8) & 255) - 128;
-                            const int dt = ((d >> 16) & 255) - 128;
+    LaneCells<W, PI> lc(lane);
+    int ct[W];
+    R gx[PI][W], gy[PI][W];            // the owned cells' values
 #pragma unroll
-                            for (int i = 0; i < PI; ++i) {
-                                const int rr = dr + par[i], ss = ds + pas[i];
-                                const bool ok = lane + 64 * i < Cfg::kPairs && rr >= 0 && rr < kTileR && ss >= 0 &&
-                                                ss < kTileS;
+    for (int a = 0; a < W; ++a) ct[a] = -1000;
 #pragma unroll
-                                for (int a = 0; a < W; ++a) {
-                                    const int tt = dt + a;
-                                    const bool in = ok && tt >= 0 && tt < nt_valid;
-                                    const int cell = in ? (tt * kTileR + rr) * kTileS + ss : 0;
-                                    qx[i][a] = in ? tre[cell] : R(0);
-                                    qy[i][a] = in ? tim[cell] : R(0);
-                                }
-                            }
-                            prev = d;
-                        }
-                        R wt[W];
+    for (int i = 0; i < PI; ++i)
 #pragma unroll
-                        for (int a = 0; a < W; ++a) wt[a] = lane_val(word, a);
-                        R px = R(0), py = R(0);
+        for (int a = 0; a < W; ++a) gx[i][a] = gy[i][a] = R(0);
+    int prev = -1;
+    for (uint32_t base = q0; base < q1; base += WB) {
+        const int n = int(min(uint32_t(WB), q1 - base));
+        R cx = R(0), cy = R(0);
+        uint32_t idx = 0;
+        if (lane < n) {
+            stage_record<R, W>(nxt, slot0 + lane, r0, s0, t0, P, coef, st);
+            cx = nxt.v[0];
+            cy = nxt.v[1];
+            idx = nxt.idx;
+        }
+        wave_sync();
+        const uint32_t vn = base + WB + uint32_t(lane);
+        if (lane < WB && vn < q1) nxt = rec[seg_index(sg, nseg, vn)];
+
+        R ox = R(0), oy = R(0);              // lane j: record j's part from this tile
+        for (int j = 0; j < n; ++j) {
+            const int slot = slot0 + j;
+            const R word = st.words[slot][wl];
+            R fu[PI], fv[PI];
 #pragma unroll
-                        for (int i = 0; i < PI; ++i) {
-                            R sx0 = R(0), sy0 = R(0), sx1 = R(0), sy1 = R(0);
+            for (int i = 0; i < PI; ++i) {
+                fu[i] = st.wuv[slot][lc.x[i]];
+                fv[i] = st.wuv[slot][W + lc.y[i]];
+            }
+            const int d = lane_bits(word, W + 2);
+            if (d != prev) {                                   // the support moved: read changed cells
+                prev = d;
+                const int dr = (d & 255) - 128, ds = ((d >> 8) & 255) - 128, dt = ((d >> 16) & 255) - 128;
+                bool mv[PI];
 #pragma unroll
-                            for (int a = 0; a < W; ++a) {
-                                if (a & 1) {
-                                    sx1 += qx[i][a] * wt[a];
-                                    sy1 += qy[i][a] * wt[a];
-                                } else {
-                                    sx0 += qx[i][a] * wt[a];
-                                    sy0 += qy[i][a] * wt[a];
-                                }
-                            }
-                            const R f = st.wuv[j][par[i]] * st.wuv[j][W + pas[i]];
-                            px += (sx0 + sx1) * f;
-                            py += (sy0 + sy1) * f;
-                        }
-                        px = wave_sum_lane63(px);
-                        py = wave_sum_lane63(py);
-                        if (lane == 63) {
-                            st.out[j][0] = px;
-                            st.out[j][1] = py;
+                for (int i = 0; i < PI; ++i) {
+                    const int nr = dr + mod_w<W>(lc.x[i] - dr), ns = ds + mod_w<W>(lc.y[i] - ds);
+                    mv[i] = nr != lc.r[i] || ns != lc.s[i];
+                    lc.r[i] = nr;
+                    lc.s[i] = ns;
+                }
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    const int nt = dt + mod_w<W>(a - dt);
+                    const bool tm = nt != ct[a];
+                    ct[a] = nt;
+#pragma unroll
+                    for (int i = 0; i < PI; ++i) {
+                        if (tm || mv[i]) {
+                            const bool in = lc.valid[i] && unsigned(lc.r[i]) < unsigned(kTileR) &&
+                                            unsigned(lc.s[i]) < unsigned(kTileS) && unsigned(nt) < unsigned(nt_valid);
+                            const int cell = in ? (nt * kTileR + lc.r[i]) * kTileS + lc.s[i] : 0;
+                            gx[i][a] = in ? tre[cell] : R(0);
+                            gy[i][a] = in ? tim[cell] : R(0);
                         }
                     }
-                    __syncthreads();
-                    // one global update per record and tile: phase exp(-i 2 pi w (n0 - 1)),
-                    // conjugate for a folded visibility
-                    if (tid < n) {
-                        const R sx = st.out[tid][0], sy = st.out[tid][1];
-                        const R cx = st.words[tid][W], cy = st.words[tid][W + 1];
-                        R ox = sx * cx - sy * cy, oy = sx * cy + sy * cx;
-                        const uint32_t idx = st.idx[tid];
-                        if (idx & 0x80000000u) oy = -oy;
-                        const size_t k = idx & 0x7fffffffu;
-                        atomicAdd(&vis[2 * k], ox);
-                        atomicAdd(&vis[2 * k + 1], oy);
-                    }
-                    __syncthreads();
                 }
             }
+            R px = R(0), py = R(0);
+#pragma unroll
+            for (int i = 0; i < PI; ++i) {
+                R sx0 = R(0), sy0 = R(0), sx1 = R(0), sy1 = R(0);
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    const R wt = lane_val(word, a);
+                    if (a & 1) {
+                        sx1 += gx[i][a] * wt;
+                        sy1 += gy[i][a] * wt;
+                    } else {
+                        sx0 += gx[i][a] * wt;
+                        sy0 += gy[i][a] * wt;
+                    }
+                }
+                const R f = fu[i] * fv[i];
+                px += (sx0 + sx1) * f;
+                py += (sy0 + sy1) * f;
+            }
+            px = wave_sum_lane63(px);
+            py = wave_sum_lane63(py);
+            const R tx = lane_val(px, 63), ty = lane_val(py, 63);
+            if (lane == j) {
+                ox = tx;
+                oy = ty;
+            }
+        }
+        wave_sync();
+        // one global update per record and tile: phase exp(-i 2 pi w (n0 - 1)),
+        // conjugate for a folded visibility
+        if (lane < n) {
+            R rx = ox * cx - oy * cy, ry = ox * cy + oy * cx;
+            if (idx & 0x80000000u) ry = -ry;
+            const size_t k = idx & 0x7fffffffu;
+            atomicAdd(&vis[2 * k], rx);
+            atomicAdd(&vis[2 * k + 1], ry);
+        }
+    }
 }
 
 // --------------------------------------------------------------- FFT passes --

@@ -86,7 +86,7 @@ struct wsg_plan {
 namespace {
 
 struct Layout {
-    size_t stack, inter, rec, rec2, count, start, cursor, bsums, skipped, total;
+    size_t stack, inter, rec, rec2, count, start, cursor, bsums, cls, skipped, total;
     int nbins, nscan;
 };
 
@@ -106,6 +106,7 @@ Layout layout_of(const wsg_plan* p, int prec, int64_t M) {
     L.start = off;   off += al256(size_t(L.nbins + 1) * 4);
     L.cursor = off;  off += al256(size_t(L.nbins) * 4);
     L.bsums = off;   off += al256(size_t(L.nscan) * 4);
+    L.cls = off;     off += al256(size_t(L.nbins) * 8 * 4);
     L.stack = off;   off += al256(nl * Np * Np * cs);
     L.inter = off;   off += al256(nl * N * Np * cs);
     L.rec = off;     off += al256(size_t(M) * rs);
@@ -149,21 +150,21 @@ void scan(const uint32_t* count, uint32_t* start, uint32_t* bsums, int n, hipStr
 // ---- compile-time dispatch over W and log2 N' ----
 
 template <typename R, int W>
-void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* start, const DevParams& P,
-                    const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
+void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
+                    const DevParams& P, const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
     if (grid)
-        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, P, coef, stack);
+        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, P, coef, stack);
     else
-        hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, P, coef,
+        hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, P, coef,
                            (const cpx<R>*)stack, vis);
 }
 
 template <typename R>
-void launch_tiles(bool grid, int W, int nblocks, const Rec<R>* rec, const uint32_t* start, const DevParams& P,
-                  const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
+void launch_tiles(bool grid, int W, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
+                  const DevParams& P, const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
     switch (W) {
 #define WSG_W(w) \
-    case w: launch_tiles_w<R, w>(grid, nblocks, rec, start, P, coef, stack, vis, s); break;
+    case w: launch_tiles_w<R, w>(grid, nblocks, rec, start, cls, P, coef, stack, vis, s); break;
         WSG_W(1) WSG_W(2) WSG_W(3) WSG_W(4) WSG_W(5) WSG_W(6) WSG_W(7) WSG_W(8)
         WSG_W(9) WSG_W(10) WSG_W(11) WSG_W(12) WSG_W(13) WSG_W(14) WSG_W(15) WSG_W(16)
 #undef WSG_W
@@ -243,6 +244,7 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
     auto* start = reinterpret_cast<uint32_t*>(w + L.start);
     auto* cursor = reinterpret_cast<uint32_t*>(w + L.cursor);
     auto* bsums = reinterpret_cast<uint32_t*>(w + L.bsums);
+    auto* cls = reinterpret_cast<uint32_t*>(w + L.cls);
     auto* skipped = reinterpret_cast<uint32_t*>(w + L.skipped);
     const bool f64 = sizeof(R) == 8;
     const R* coef = f64 ? reinterpret_cast<const R*>(plan->poly64) : reinterpret_cast<const R*>(plan->poly32);
@@ -267,20 +269,20 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
                 hipLaunchKernelGGL((k_bin_scatter<R, false>), dim3(vblocks), dim3(256), 0, s, uvw,
                                    (const cpx<R>*)nullptr, (long long)M, P, (const uint32_t*)start, cursor, rec_bin);
             hipLaunchKernelGGL(k_bin_local_sort<R>, dim3(L.nbins), dim3(256), 0, s, (const Rec<R>*)rec_bin, rec,
-                               (const uint32_t*)start, P);
+                               (const uint32_t*)start, cls, P);
         }
     }
     if (grid) {
         {
             StageMark mark(s, 1);
-            launch_tiles<R>(true, P.W, L.nbins, rec, start, P, coef, stack, nullptr, s);
+            launch_tiles<R>(true, P.W, L.nbins, rec, start, cls, P, coef, stack, nullptr, s);
         }
         launch_fft<R>(true, plan->log2_np, P, stack, inter, tw, corr, nullptr, static_cast<R*>(out), s);
     } else {
         launch_fft<R>(false, plan->log2_np, P, stack, inter, tw, corr, static_cast<const R*>(in), nullptr, s);
         StageMark mark(s, 7);
         fill<R>(static_cast<R*>(out), size_t(2 * M), R(0), s);
-        if (M > 0) launch_tiles<R>(false, P.W, L.nbins, rec, start, P, coef, stack, static_cast<R*>(out), s);
+        if (M > 0) launch_tiles<R>(false, P.W, L.nbins, rec, start, cls, P, coef, stack, static_cast<R*>(out), s);
     }
     WSG_HIP(hipGetLastError());
     return WSG_OK;
