@@ -271,53 +271,14 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
 // records that reach the tile (from its own bin and the seven bins one tile
 // back, selected by touch class) form a virtual list of at most 64 ranges of
 // the record array.  The list is cut into four contiguous quarters, one per
-// wave; the waves work independently (no block barrier between the tile's
-// set-up and its write-out).  A wave walks its quarter in rounds of kWaveBatch
-// records: each lane stages one record (kernel weights by Horner's rule) into
-// the wave's LDS slots while it already holds its next record in registers.
-//
-// Lanes follow the residue-class scheme of Romein (2012), extended to three
-// axes: lane (x, y) owns, among the W x W x W support cells of a record, the W
-// cells whose u and v indices are congruent to x and y modulo W, one per layer
-// residue a (the cell whose layer is congruent to a).  For a record with
-// support start (dr, ds, dt) that is u-cell dr + ((x - dr) mod W), v-cell
-// ds + ((y - ds) mod W) and layer dt + ((a - dt) mod W).  The staged weights
-// are stored rotated by the support start, so that lane x reads its u weight at
-// position x whatever the record.  When consecutive records move their support
-// by one cell, only the lanes and layer residues whose owned cell changed
-//   scatter: add their register sums into the LDS tile (LDS atomics: the four
-//            waves share the tile) and restart from zero;
-//   gather:  read their new cell from the LDS tile;
-// everything else stays in registers.  Records are sorted by support start
-// inside each touch class, so consecutive supports mostly coincide or move by
-// one cell.  The gather sums each record's W^3 terms over the wave (DPP) and
-// adds the tile's part to the visibility with one global atomic.  Each tile is
-// read or written to HBM once.
+// wave; the waves work independently between the tile's set-up and its
+// write-out, and each holds its next records in registers while it works on
+// the current ones.  Each tile is read or written to HBM once.
 
 // Kernel polynomial degree in nu per precision (the host fits both).
 template <typename R>
 struct KernelDegree {
     static constexpr int value = sizeof(R) == 8 ? 16 : 10;
-};
-
-template <typename R, int W>
-struct TileCfg {
-    static constexpr int kDeg = KernelDegree<R>::value;
-    static constexpr int kWaveBatch = sizeof(R) == 8 ? 32 : 64;    // records per wave round
-    static constexpr int kSlots = 4 * kWaveBatch;
-    static constexpr int kPairs = W * W;
-    static constexpr int kPI = (kPairs + 63) / 64;     // (x, y) residue pairs per lane
-    static constexpr int kCells = kTileT * kTileR * kTileS;
-};
-
-template <typename R, int W>
-struct TileStage {
-    // words: layer weights C(s_a - nu_w) rotated (position (a + dt) mod W holds
-    // a), then the value (2), then the packed support start
-    // (dr + 128) | (ds + 128) << 8 | (dt + 128) << 16
-    R words[TileCfg<R, W>::kSlots][W + 3];
-    // u weights rotated by dr, then v weights rotated by ds
-    R wuv[TileCfg<R, W>::kSlots][2 * W];
 };
 
 // The records that reach one tile: ranges [lo[g], lo[g] + off[g+1] - off[g])
@@ -377,21 +338,6 @@ __device__ __forceinline__ uint32_t seg_index(const TileSegs& sg, int n, uint32_
     return sg.lo[g] + (v - sg.off[g]);
 }
 
-__device__ __forceinline__ float bits_to_word(int v, float) { return __int_as_float(v); }
-__device__ __forceinline__ double bits_to_word(int v, double) { return __hiloint2double(0, v); }
-
-// value of `v` in lane l (l wave-uniform), as a wave-uniform (scalar) value
-__device__ __forceinline__ float lane_val(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ double lane_val(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ int lane_bits(float v, int l) { return __builtin_amdgcn_readlane(__float_as_int(v), l); }
-__device__ __forceinline__ int lane_bits(double v, int l) { return __builtin_amdgcn_readlane(__double2loint(v), l); }
-
 // Signed offset of a support start from the tile origin along a periodic axis.
 __device__ __forceinline__ int wrap_offset(int first, int origin, int Np) {
     int d = first - origin;
@@ -406,25 +352,17 @@ __device__ __forceinline__ int mod_w(int x) {
     return (x + 16 * W) % W;
 }
 
-// Orders this wave's LDS accesses around a hand-over between its lanes.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ int tile_of_block(const DevParams& P) {
+    return xcd_interleave<4>(blockIdx.x, P.nbt * P.nbs * P.nbr);
 }
 
-// Stage one record into slot `slot`: kernel weights on the three axes, rotated
-// by the support start, and the packed support start relative to the tile.
+// Kernel weights of one record on the three axes by Horner's rule; the same
+// least-misfit function on every axis, so each coefficient read (an LDS
+// broadcast) feeds three chains.
 template <typename R, int W>
-__device__ __forceinline__ void stage_record(const Rec<R>& r, int slot, int r0, int s0, int t0, const DevParams& P,
-                                             const R* __restrict__ coef, TileStage<R, W>& st) {
-    constexpr int D = TileCfg<R, W>::kDeg;
-    const int dr = wrap_offset(int(r.ruv & 0xffffu), r0, P.Np);
-    const int ds = wrap_offset(int(r.ruv >> 16), s0, P.Np);
-    const int dt = int(r.rt) - t0;
-    const int pr = mod_w<W>(dr), ps = mod_w<W>(ds), pt = mod_w<W>(dt);
-    // the same least-misfit function on every axis: each coefficient read
-    // (an LDS broadcast) feeds the three Horner chains
+__device__ __forceinline__ void record_weights(const Rec<R>& r, const R* __restrict__ coef, R (&wu)[W], R (&wv)[W],
+                                               R (&wt)[W]) {
+    constexpr int D = KernelDegree<R>::value;
 #pragma unroll
     for (int a = 0; a < W; ++a) {
         const R* c = coef + a * (D + 1);
@@ -436,40 +374,55 @@ __device__ __forceinline__ void stage_record(const Rec<R>& r, int slot, int r0, 
             hv = hv * r.nu[1] + ck;
             ht = ht * r.nu[2] + ck;
         }
-        int ku = pr + a, kv = ps + a, kt = pt + a;
-        ku -= ku >= W ? W : 0;
-        kv -= kv >= W ? W : 0;
-        kt -= kt >= W ? W : 0;
-        st.wuv[slot][ku] = hu;
-        st.wuv[slot][W + kv] = hv;
-        st.words[slot][kt] = ht;
+        wu[a] = hu;
+        wv[a] = hv;
+        wt[a] = ht;
     }
-    st.words[slot][W] = r.v[0];
-    st.words[slot][W + 1] = r.v[1];
-    st.words[slot][W + 2] = bits_to_word((dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16), R(0));
 }
 
-__device__ __forceinline__ int tile_of_block(const DevParams& P) {
-    return xcd_interleave<4>(blockIdx.x, P.nbt * P.nbs * P.nbr);
+// Orders this wave's LDS accesses around a hand-over between its lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The lane's residue pairs and its cells for support start (dr, ds).
-template <int W, int PI>
-struct LaneCells {
-    int x[PI], y[PI];
-    bool valid[PI];
-    int r[PI], s[PI];              // owned u- and v-cells (tile-relative)
-    __device__ explicit LaneCells(int lane) {
-#pragma unroll
-        for (int i = 0; i < PI; ++i) {
-            const int p = lane + 64 * i;
-            valid[i] = p < W * W;
-            const int pc = min(p, W * W - 1);
-            x[i] = pc / W;
-            y[i] = pc % W;
-            r[i] = s[i] = -1000;
-        }
-    }
+__device__ __forceinline__ float bits_to_word(int v, float) { return __int_as_float(v); }
+__device__ __forceinline__ double bits_to_word(int v, double) { return __hiloint2double(0, v); }
+__device__ __forceinline__ int word_bits(float v) { return __float_as_int(v); }
+__device__ __forceinline__ int word_bits(double v) { return __double2loint(v); }
+
+// Scatter: residue classes (Romein 2012, extended to three axes).  Lane (x, y)
+// owns, among the W x W x W support cells of a record, the W cells whose u and
+// v indices are congruent to x and y modulo W, one per layer residue a: for
+// support start (dr, ds, dt) the u-cell dr + ((x - dr) mod W), the v-cell
+// ds + ((y - ds) mod W) and the layer dt + ((a - dt) mod W).  Each lane stages
+// one record per round into its wave's slots: the u weights times the value
+// and the v weights rotated by the support start (so lane x reads position x
+// whatever the record), and the layer weights rotated by dt with the packed
+// support start, read by the whole wave as broadcasts.  Sums stay in registers
+// while the owned cell stays the same; when the support moves, the lanes (or
+// layer residues) whose owned cell changed add their sums to the LDS tile
+// (atomics: the four waves share it) and restart from zero.  Records are sorted
+// by support start inside each touch class, so supports mostly coincide or
+// move by one cell.
+template <typename R, int W>
+struct ScatterCfg {
+    static constexpr int kWaveBatch = sizeof(R) == 8 ? 32 : 64;    // records per wave round
+    static constexpr int kSlots = 4 * kWaveBatch;
+    static constexpr int kPairs = W * W;
+    static constexpr int kPI = (kPairs + 63) / 64;                // (x, y) residue pairs per lane
+    static constexpr int kCells = kTileT * kTileR * kTileS;
+    static constexpr int kWords = ((W + 1) * sizeof(R) + 15) / 16 * 16 / sizeof(R);   // 16-byte rows
+};
+
+template <typename R, int W>
+struct __align__(16) ScatterStage {
+    // layer weights rotated (position (a + dt) mod W holds C(s_a - nu_w)),
+    // then the packed support start (dr + 128) | (ds + 128) << 8 | (dt + 128) << 16
+    R words[ScatterCfg<R, W>::kSlots][ScatterCfg<R, W>::kWords];
+    // value times u weights (real, imaginary), rotated by dr; v weights rotated by ds
+    R wuv[ScatterCfg<R, W>::kSlots][3 * W];
 };
 
 template <typename R, int W>
@@ -477,12 +430,12 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
                                                     const uint32_t* __restrict__ start,
                                                     const uint32_t* __restrict__ cls, DevParams P,
                                                     const R* __restrict__ coef_g, cpx<R>* __restrict__ stack) {
-    using Cfg = TileCfg<R, W>;
-    constexpr int PI = Cfg::kPI, WB = Cfg::kWaveBatch;
+    using Cfg = ScatterCfg<R, W>;
+    constexpr int PI = Cfg::kPI, WB = Cfg::kWaveBatch, D = KernelDegree<R>::value;
     __shared__ R tre[Cfg::kCells];
     __shared__ R tim[Cfg::kCells];
-    __shared__ TileStage<R, W> st;
-    __shared__ R coef[W * (Cfg::kDeg + 1)];
+    __shared__ ScatterStage<R, W> st;
+    __shared__ R coef[W * (D + 1)];
     __shared__ TileSegs sg;
 
     const int tile = tile_of_block(P);
@@ -491,11 +444,10 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     const int nt_valid = min(kTileT, P.n_layers - t0);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wl = min(lane, W + 2);
 
     if (tid < 64) tile_segments(start, cls, P, bt, bs, br, sg);
     for (int i = tid; i < Cfg::kCells; i += 256) tre[i] = tim[i] = R(0);
-    for (int i = tid; i < W * (Cfg::kDeg + 1); i += 256) coef[i] = coef_g[i];
+    for (int i = tid; i < W * (D + 1); i += 256) coef[i] = coef_g[i];
     __syncthreads();
     const int nseg = sg.n;
     const uint32_t total = sg.off[nseg];
@@ -504,8 +456,19 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     const uint32_t q0 = min(total, quarter * uint32_t(wv)), q1 = min(total, q0 + quarter);
 
     if (q1 > q0) {
-        LaneCells<W, PI> lc(lane);
-        int ct[W];                               // owned layer per residue (wave-uniform)
+        // the lane's residue pairs, owned cells and register sums
+        int px[PI], py[PI], cr[PI], cs[PI];
+        bool pv[PI];
+#pragma unroll
+        for (int i = 0; i < PI; ++i) {
+            const int p = lane + 64 * i;
+            pv[i] = p < Cfg::kPairs;
+            const int pc = min(p, Cfg::kPairs - 1);
+            px[i] = pc / W;
+            py[i] = pc % W;
+            cr[i] = cs[i] = -1000;
+        }
+        int ct[W];                                   // owned layer per residue (wave-uniform)
         R ax[PI][W], ay[PI][W];
 #pragma unroll
         for (int a = 0; a < W; ++a) ct[a] = -1000;
@@ -513,85 +476,114 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
         for (int i = 0; i < PI; ++i)
 #pragma unroll
             for (int a = 0; a < W; ++a) ax[i][a] = ay[i][a] = R(0);
-        auto add_cell = [&](int i, int t, R vx, R vy) {
-            if (lc.valid[i] && unsigned(lc.r[i]) < unsigned(kTileR) && unsigned(lc.s[i]) < unsigned(kTileS) &&
+        // add sum (i, a) to its owned cell if that cell is in the tile
+        auto add_cell = [&](int i, int a) {
+            const int t = ct[a];
+            if (pv[i] && unsigned(cr[i]) < unsigned(kTileR) && unsigned(cs[i]) < unsigned(kTileS) &&
                 unsigned(t) < unsigned(nt_valid)) {
-                const int cell = (t * kTileR + lc.r[i]) * kTileS + lc.s[i];
-                atomicAdd(&tre[cell], vx);
-                atomicAdd(&tim[cell], vy);
+                const int cell = (t * kTileR + cr[i]) * kTileS + cs[i];
+                atomicAdd(&tre[cell], ax[i][a]);
+                atomicAdd(&tim[cell], ay[i][a]);
+            }
+            ax[i][a] = ay[i][a] = R(0);
+        };
+        int prev = -1, prev_dt = -1000;
+        // the support starts at packed d: flush the sums of owned cells that change
+        auto move_to = [&](int d) {
+            prev = d;
+            const int dr = (d & 255) - 128, ds = ((d >> 8) & 255) - 128, dt = ((d >> 16) & 255) - 128;
+            const int mr = mod_w<W>(-dr), ms = mod_w<W>(-ds);
+#pragma unroll
+            for (int i = 0; i < PI; ++i) {
+                int xr = px[i] + mr, ys = py[i] + ms;
+                xr -= xr >= W ? W : 0;
+                ys -= ys >= W ? W : 0;
+                const int nr = dr + xr, ns = ds + ys;
+                if (nr != cr[i] || ns != cs[i]) {
+#pragma unroll
+                    for (int a = 0; a < W; ++a) add_cell(i, a);
+                    cr[i] = nr;
+                    cs[i] = ns;
+                }
+            }
+            if (dt != prev_dt) {
+                prev_dt = dt;
+                const int mt = mod_w<W>(-dt);
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    int k = a + mt;
+                    k -= k >= W ? W : 0;
+                    const int nt = dt + k;
+                    if (nt != ct[a]) {
+#pragma unroll
+                        for (int i = 0; i < PI; ++i) add_cell(i, a);
+                        ct[a] = nt;
+                    }
+                }
             }
         };
 
         const int slot0 = wv * WB;
         Rec<R> nxt;
-        if (q0 + uint32_t(lane) < q1 && lane < WB) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(lane))];
-        int prev = -1;
+        if (lane < WB && q0 + uint32_t(lane) < q1) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(lane))];
         for (uint32_t base = q0; base < q1; base += WB) {
             const int n = int(min(uint32_t(WB), q1 - base));
-            if (lane < n) stage_record<R, W>(nxt, slot0 + lane, r0, s0, t0, P, coef, st);
+            if (lane < n) {
+                // stage: rotated weights, value folded into the u weights
+                const int dr = wrap_offset(int(nxt.ruv & 0xffffu), r0, P.Np);
+                const int ds = wrap_offset(int(nxt.ruv >> 16), s0, P.Np);
+                const int dt = int(nxt.rt) - t0;
+                R wu[W], wv_[W], wt[W];
+                record_weights<R, W>(nxt, coef, wu, wv_, wt);
+                const int pr = mod_w<W>(dr), ps = mod_w<W>(ds), pt = mod_w<W>(dt);
+                const int slot = slot0 + lane;
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    int ku = pr + a, kv = ps + a, kt = pt + a;
+                    ku -= ku >= W ? W : 0;
+                    kv -= kv >= W ? W : 0;
+                    kt -= kt >= W ? W : 0;
+                    st.wuv[slot][ku] = nxt.v[0] * wu[a];
+                    st.wuv[slot][W + ku] = nxt.v[1] * wu[a];
+                    st.wuv[slot][2 * W + kv] = wv_[a];
+                    st.words[slot][kt] = wt[a];
+                }
+                st.words[slot][W] = bits_to_word((dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16), R(0));
+            }
             wave_sync();
             const uint32_t vn = base + WB + uint32_t(lane);
             if (lane < WB && vn < q1) nxt = rec[seg_index(sg, nseg, vn)];
 
             for (int j = 0; j < n; ++j) {
                 const int slot = slot0 + j;
-                const R word = st.words[slot][wl];                 // one word per lane
-                R fu[PI], fv[PI];
+                R wt[W];
+#pragma unroll
+                for (int a = 0; a < W; ++a) wt[a] = st.words[slot][a];       // broadcast
+                const int d = __builtin_amdgcn_readfirstlane(word_bits(st.words[slot][W]));
+                R fx[PI], fy[PI], fv[PI];
 #pragma unroll
                 for (int i = 0; i < PI; ++i) {
-                    fu[i] = st.wuv[slot][lc.x[i]];
-                    fv[i] = st.wuv[slot][W + lc.y[i]];
+                    fx[i] = st.wuv[slot][px[i]];
+                    fy[i] = st.wuv[slot][W + px[i]];
+                    fv[i] = st.wuv[slot][2 * W + py[i]];
                 }
-                const int d = lane_bits(word, W + 2);
-                if (d != prev) {                                   // the support moved
-                    prev = d;
-                    const int dr = (d & 255) - 128, ds = ((d >> 8) & 255) - 128, dt = ((d >> 16) & 255) - 128;
-                    bool mv[PI];
-                    int nr[PI], ns[PI];
-#pragma unroll
-                    for (int i = 0; i < PI; ++i) {
-                        nr[i] = dr + mod_w<W>(lc.x[i] - dr);
-                        ns[i] = ds + mod_w<W>(lc.y[i] - ds);
-                        mv[i] = nr[i] != lc.r[i] || ns[i] != lc.s[i];
-                    }
-#pragma unroll
-                    for (int a = 0; a < W; ++a) {
-                        const int nt = dt + mod_w<W>(a - dt);
-                        const bool tm = nt != ct[a];
-#pragma unroll
-                        for (int i = 0; i < PI; ++i) {
-                            if (tm || mv[i]) {
-                                add_cell(i, ct[a], ax[i][a], ay[i][a]);
-                                ax[i][a] = ay[i][a] = R(0);
-                            }
-                        }
-                        ct[a] = nt;
-                    }
-#pragma unroll
-                    for (int i = 0; i < PI; ++i) {
-                        lc.r[i] = nr[i];
-                        lc.s[i] = ns[i];
-                    }
-                }
-                const R vx = lane_val(word, W), vy = lane_val(word, W + 1);
+                if (d != prev) move_to(d);
 #pragma unroll
                 for (int i = 0; i < PI; ++i) {
-                    const R f = fu[i] * fv[i];
-                    const R fx = vx * f, fy = vy * f;
+                    const R gx = fx[i] * fv[i], gy = fy[i] * fv[i];
 #pragma unroll
                     for (int a = 0; a < W; ++a) {
-                        const R wt = lane_val(word, a);
-                        ax[i][a] += fx * wt;
-                        ay[i][a] += fy * wt;
+                        ax[i][a] += gx * wt[a];
+                        ay[i][a] += gy * wt[a];
                     }
                 }
             }
             wave_sync();
         }
 #pragma unroll
-        for (int a = 0; a < W; ++a)
+        for (int i = 0; i < PI; ++i)
 #pragma unroll
-            for (int i = 0; i < PI; ++i) add_cell(i, ct[a], ax[i][a], ay[i][a]);
+            for (int a = 0; a < W; ++a) add_cell(i, a);
     }
     __syncthreads();
     // write the tile: rows of kTileS cells
@@ -601,18 +593,31 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     }
 }
 
+// Gather: lanes over records.  The tile sits in LDS as complex cells with a
+// zero guard of 17 (W - 1) cells before and after, so that for any support
+// start (dr, ds) in [-(W-1), 15] the cell address base + 16 x + y of every
+// support offset is inside the array.  Each lane evaluates its own record's
+// weights, sets those of out-of-tile indices to zero (the cells read there are
+// finite neighbours or guard zeros), clamps the layer of each residue and sums
+// the W^3 products; no cross-lane reduction is needed.
+template <typename R, int W>
+struct GatherCfg {
+    static constexpr int kGuard = 17 * (W - 1);
+    static constexpr int kCells = kTileT * kTileR * kTileS;
+    static constexpr int kLen = kCells + 2 * kGuard;
+};
+
 template <typename R, int W>
 __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__ rec,
                                                       const uint32_t* __restrict__ start,
                                                       const uint32_t* __restrict__ cls, DevParams P,
                                                       const R* __restrict__ coef_g,
                                                       const cpx<R>* __restrict__ stack, R* __restrict__ vis) {
-    using Cfg = TileCfg<R, W>;
-    constexpr int PI = Cfg::kPI, WB = Cfg::kWaveBatch;
-    __shared__ R tre[Cfg::kCells];
-    __shared__ R tim[Cfg::kCells];
-    __shared__ TileStage<R, W> st;
-    __shared__ R coef[W * (Cfg::kDeg + 1)];
+    using G = GatherCfg<R, W>;
+    constexpr int D = KernelDegree<R>::value;
+    constexpr int WB = 64;
+    __shared__ cpx<R> g[G::kLen];
+    __shared__ R coef[W * (D + 1)];
     __shared__ TileSegs sg;
 
     const int tile = tile_of_block(P);
@@ -621,10 +626,9 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     const int nt_valid = min(kTileT, P.n_layers - t0);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wl = min(lane, W + 2);
 
     if (tid < 64) tile_segments(start, cls, P, bt, bs, br, sg);
-    for (int i = tid; i < W * (Cfg::kDeg + 1); i += 256) coef[i] = coef_g[i];
+    for (int i = tid; i < W * (D + 1); i += 256) coef[i] = coef_g[i];
     __syncthreads();
     const int nseg = sg.n;
     const uint32_t total = sg.off[nseg];
@@ -632,118 +636,65 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     const uint32_t quarter = (total + 3) / 4;
     const uint32_t q0 = min(total, quarter * uint32_t(wv)), q1 = min(total, q0 + quarter);
 
-    const int slot0 = wv * WB;
     Rec<R> nxt;
-    if (q0 + uint32_t(lane) < q1 && lane < WB) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(lane))];
-    for (int i = tid; i < nt_valid * kTileR * kTileS; i += 256) {
-        const int ss = i % kTileS, rr = (i / kTileS) % kTileR, tt = i / (kTileR * kTileS);
-        const cpx<R> q = stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)];
-        tre[i] = q.x;
-        tim[i] = q.y;
+    if (q0 + uint32_t(lane) < q1) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(lane))];
+    for (int i = tid; i < G::kLen; i += 256) {
+        const int c = i - G::kGuard;
+        cpx<R> q{R(0), R(0)};
+        if (c >= 0 && c < nt_valid * kTileR * kTileS) {
+            const int ss = c % kTileS, rr = (c / kTileS) % kTileR, tt = c / (kTileR * kTileS);
+            q = stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)];
+        }
+        g[i] = q;
     }
     __syncthreads();
-    if (q1 <= q0) return;
 
-    LaneCells<W, PI> lc(lane);
-    int ct[W];
-    R gx[PI][W], gy[PI][W];            // the owned cells' values
-#pragma unroll
-    for (int a = 0; a < W; ++a) ct[a] = -1000;
-#pragma unroll
-    for (int i = 0; i < PI; ++i)
-#pragma unroll
-        for (int a = 0; a < W; ++a) gx[i][a] = gy[i][a] = R(0);
-    int prev = -1;
     for (uint32_t base = q0; base < q1; base += WB) {
-        const int n = int(min(uint32_t(WB), q1 - base));
-        R cx = R(0), cy = R(0);
-        uint32_t idx = 0;
-        if (lane < n) {
-            stage_record<R, W>(nxt, slot0 + lane, r0, s0, t0, P, coef, st);
-            cx = nxt.v[0];
-            cy = nxt.v[1];
-            idx = nxt.idx;
-        }
-        wave_sync();
+        const bool live = base + uint32_t(lane) < q1;
+        const Rec<R> r = nxt;
         const uint32_t vn = base + WB + uint32_t(lane);
-        if (lane < WB && vn < q1) nxt = rec[seg_index(sg, nseg, vn)];
+        if (vn < q1) nxt = rec[seg_index(sg, nseg, vn)];
+        if (!live) continue;
 
-        R ox = R(0), oy = R(0);              // lane j: record j's part from this tile
-        for (int j = 0; j < n; ++j) {
-            const int slot = slot0 + j;
-            const R word = st.words[slot][wl];
-            R fu[PI], fv[PI];
+        const int dr = wrap_offset(int(r.ruv & 0xffffu), r0, P.Np);
+        const int ds = wrap_offset(int(r.ruv >> 16), s0, P.Np);
+        const int dt = int(r.rt) - t0;
+        R wu[W], wv_[W], wt[W];
+        record_weights<R, W>(r, coef, wu, wv_, wt);
 #pragma unroll
-            for (int i = 0; i < PI; ++i) {
-                fu[i] = st.wuv[slot][lc.x[i]];
-                fv[i] = st.wuv[slot][W + lc.y[i]];
-            }
-            const int d = lane_bits(word, W + 2);
-            if (d != prev) {                                   // the support moved: read changed cells
-                prev = d;
-                const int dr = (d & 255) - 128, ds = ((d >> 8) & 255) - 128, dt = ((d >> 16) & 255) - 128;
-                bool mv[PI];
-#pragma unroll
-                for (int i = 0; i < PI; ++i) {
-                    const int nr = dr + mod_w<W>(lc.x[i] - dr), ns = ds + mod_w<W>(lc.y[i] - ds);
-                    mv[i] = nr != lc.r[i] || ns != lc.s[i];
-                    lc.r[i] = nr;
-                    lc.s[i] = ns;
-                }
-#pragma unroll
-                for (int a = 0; a < W; ++a) {
-                    const int nt = dt + mod_w<W>(a - dt);
-                    const bool tm = nt != ct[a];
-                    ct[a] = nt;
-#pragma unroll
-                    for (int i = 0; i < PI; ++i) {
-                        if (tm || mv[i]) {
-                            const bool in = lc.valid[i] && unsigned(lc.r[i]) < unsigned(kTileR) &&
-                                            unsigned(lc.s[i]) < unsigned(kTileS) && unsigned(nt) < unsigned(nt_valid);
-                            const int cell = in ? (nt * kTileR + lc.r[i]) * kTileS + lc.s[i] : 0;
-                            gx[i][a] = in ? tre[cell] : R(0);
-                            gy[i][a] = in ? tim[cell] : R(0);
-                        }
-                    }
-                }
-            }
-            R px = R(0), py = R(0);
-#pragma unroll
-            for (int i = 0; i < PI; ++i) {
-                R sx0 = R(0), sy0 = R(0), sx1 = R(0), sy1 = R(0);
-#pragma unroll
-                for (int a = 0; a < W; ++a) {
-                    const R wt = lane_val(word, a);
-                    if (a & 1) {
-                        sx1 += gx[i][a] * wt;
-                        sy1 += gy[i][a] * wt;
-                    } else {
-                        sx0 += gx[i][a] * wt;
-                        sy0 += gy[i][a] * wt;
-                    }
-                }
-                const R f = fu[i] * fv[i];
-                px += (sx0 + sx1) * f;
-                py += (sy0 + sy1) * f;
-            }
-            px = wave_sum_lane63(px);
-            py = wave_sum_lane63(py);
-            const R tx = lane_val(px, 63), ty = lane_val(py, 63);
-            if (lane == j) {
-                ox = tx;
-                oy = ty;
-            }
+        for (int a = 0; a < W; ++a) {
+            wu[a] = unsigned(dr + a) < unsigned(kTileR) ? wu[a] : R(0);
+            wv_[a] = unsigned(ds + a) < unsigned(kTileS) ? wv_[a] : R(0);
+            wt[a] = unsigned(dt + a) < unsigned(nt_valid) ? wt[a] : R(0);
         }
-        wave_sync();
-        // one global update per record and tile: phase exp(-i 2 pi w (n0 - 1)),
-        // conjugate for a folded visibility
-        if (lane < n) {
-            R rx = ox * cx - oy * cy, ry = ox * cy + oy * cx;
-            if (idx & 0x80000000u) ry = -ry;
-            const size_t k = idx & 0x7fffffffu;
-            atomicAdd(&vis[2 * k], rx);
-            atomicAdd(&vis[2 * k + 1], ry);
+        const cpx<R>* row = g + (G::kGuard + dr * kTileS + ds);
+        R sx = R(0), sy = R(0);
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const int tt = min(max(dt + a, 0), kTileT - 1);
+            const cpx<R>* pa = row + tt * (kTileR * kTileS);
+            R ax = R(0), ay = R(0);
+#pragma unroll
+            for (int x = 0; x < W; ++x) {
+                R bx = R(0), by = R(0);
+#pragma unroll
+                for (int y = 0; y < W; ++y) {
+                    const cpx<R> q = pa[x * kTileS + y];
+                    bx += q.x * wv_[y];
+                    by += q.y * wv_[y];
+                }
+                ax += bx * wu[x];
+                ay += by * wu[x];
+            }
+            sx += ax * wt[a];
+            sy += ay * wt[a];
         }
+        // phase exp(-i 2 pi w (n0 - 1)), conjugate for a folded visibility
+        R ox = sx * r.v[0] - sy * r.v[1], oy = sx * r.v[1] + sy * r.v[0];
+        if (r.idx & 0x80000000u) oy = -oy;
+        const size_t k = r.idx & 0x7fffffffu;
+        atomicAdd(&vis[2 * k], ox);
+        atomicAdd(&vis[2 * k + 1], oy);
     }
 }
 
