@@ -264,6 +264,27 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
     }
 }
 
+// Tile occupancy: a tile is marked when any of the eight bins whose
+// visibilities can reach it (its own and the seven one tile back) is non-empty.
+// Only marked tiles of the stack are written (grid) or filled (degrid); the FFT
+// passes treat unmarked tiles as zero (grid) or skip them (degrid).
+__global__ void k_tile_occupancy(const uint32_t* __restrict__ start, DevParams P, uint8_t* __restrict__ occ) {
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nt = P.nbt * P.nbs * P.nbr;
+    if (tile >= nt) return;
+    const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
+    uint32_t any = 0;
+    for (int it = 0; it < 2; ++it) {
+        if (bt - it < 0) continue;
+        for (int is = 0; is < 2; ++is)
+            for (int ir = 0; ir < 2; ++ir) {
+                const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
+                any |= start[bin + 1] - start[bin];
+            }
+    }
+    occ[tile] = any ? 1 : 0;
+}
+
 // ------------------------------------------------ 3-D scatter / gather tiles --
 //
 // One 256-thread block owns one tile of kTileT layers x kTileR u-cells x
@@ -428,7 +449,8 @@ struct __align__(16) ScatterStage {
 template <typename R, int W>
 __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ rec,
                                                     const uint32_t* __restrict__ start,
-                                                    const uint32_t* __restrict__ cls, DevParams P,
+                                                    const uint32_t* __restrict__ cls,
+                                                    const uint8_t* __restrict__ occ, DevParams P,
                                                     const R* __restrict__ coef_g, cpx<R>* __restrict__ stack) {
     using Cfg = ScatterCfg<R, W>;
     constexpr int PI = Cfg::kPI, WB = Cfg::kWaveBatch, D = KernelDegree<R>::value;
@@ -439,6 +461,7 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     __shared__ TileSegs sg;
 
     const int tile = tile_of_block(P);
+    if (!occ[tile]) return;     // no visibility reaches it: left unwritten, read as zero
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0);
@@ -711,8 +734,9 @@ struct FftCfg {
     static constexpr int N = 1 << LOGN;
     static constexpr int T = N / 16;
     static constexpr int kLineBytes = LinePad<N>::size * int(sizeof(cpx<R>));
-    // lines per block for the transposed passes: enough for >= 64-byte runs, within LDS
-    static constexpr int kNLt0 = (160 * 1024 - 4096) / kLineBytes;
+    // lines per block for the transposed passes: as many as fit in half the LDS,
+    // so that two blocks share a CU and overlap their load and transform phases
+    static constexpr int kNLt0 = (80 * 1024 - 2048) / kLineBytes;
     static constexpr int kNLt1 = kNLt0 < 1 ? 1 : kNLt0;
     static constexpr int kNLt2 = kNLt1 >= 16 ? 16 : kNLt1 >= 8 ? 8 : kNLt1 >= 4 ? 4 : kNLt1 >= 2 ? 2 : 1;
     static constexpr int kNLt = (kNLt2 * T > 1024) ? 1024 / T : kNLt2;   // a power of two
@@ -721,34 +745,61 @@ struct FftCfg {
 };
 
 // grid pass A: IFFT along s of stack rows [t][r][:], keep image rows q, write
-// the intermediate transposed [t][q][r].
+// the intermediate transposed [t][q][r].  One block per layer and row of tiles
+// (kTileR stack rows, taken NL at a time); the next NL rows are loaded while
+// the current ones are transformed.  Unmarked tiles are read as zero, and a
+// row of tiles with none marked is written as zeros without a transform.
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
-    k_grid_fft_a(const cpx<R>* __restrict__ stack, cpx<R>* __restrict__ inter, const cpx<R>* __restrict__ tw,
-                 int N, int n_layers) {
+    k_grid_fft_a(const cpx<R>* __restrict__ stack, const uint8_t* __restrict__ occ, cpx<R>* __restrict__ inter,
+                 const cpx<R>* __restrict__ tw, int N, int n_layers, int nbr) {
     using C = FftCfg<R, LOGN>;
-    constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size;
+    constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size, NG = kTileR / NL;
+    static_assert(kTileR % NL == 0, "a row of tiles is a whole number of line groups");
     __shared__ cpx<R> buf[NL * LP];
-    const int blocks_per_plane = Np / NL;
+    const int rows = Np / kTileR;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int t = lb / blocks_per_plane, r0 = (lb % blocks_per_plane) * NL;
+    const int t = lb / rows, rt = lb % rows;
     const int line = threadIdx.x / T, j = threadIdx.x % T;
     cpx<R>* lbuf = buf + line * LP;
-    const cpx<R>* src = stack + ((size_t)t * Np + (r0 + line)) * Np;
-    cpx<R> v[16];
+    // tile (t / 16, s / 16, rt) holds s = j + T k
+    const uint8_t* orow = occ + (size_t)(t / kTileT) * (Np / kTileS) * nbr + rt;
+    bool on[16], any = false;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = src[j + T * k];
-    fft_line<R, LOGN, +1>(v, lbuf, tw, j);
-    __syncthreads();
+    for (int k = 0; k < 16; ++k) {
+        on[k] = orow[(size_t)((j + T * k) / kTileS) * nbr] != 0;
+        any = any || on[k];
+    }
+    cpx<R>* dst0 = inter + (size_t)t * N * Np + rt * kTileR;
+    if (!__syncthreads_or(any)) {
+        for (int idx = threadIdx.x; idx < N * kTileR; idx += NL * T)
+            dst0[(size_t)(idx / kTileR) * Np + idx % kTileR] = cpx<R>{R(0), R(0)};
+        return;
+    }
+    auto load = [&](int g, cpx<R> (&v)[16]) {
+        const cpx<R>* src = stack + ((size_t)t * Np + (rt * kTileR + g * NL + line)) * Np;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) lbuf[lpad(j + T * k)] = v[k];
-    __syncthreads();
-    cpx<R>* dst = inter + (size_t)t * N * Np + r0;
+        for (int k = 0; k < 16; ++k) v[k] = on[k] ? src[j + T * k] : cpx<R>{R(0), R(0)};
+    };
     const int half = N / 2;
-    for (int idx = threadIdx.x; idx < N * NL; idx += NL * T) {
-        const int q = idx / NL, l = idx % NL;
-        const int f = (q - half) & (Np - 1);
-        dst[(size_t)q * Np + l] = buf[l * LP + lpad(f)];
+    cpx<R> nx[16];
+    load(0, nx);
+    for (int g = 0; g < NG; ++g) {
+        cpx<R> v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = nx[k];
+        if (g + 1 < NG) load(g + 1, nx);
+        fft_line<R, LOGN, +1>(v, lbuf, tw, j);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lbuf[lpad(j + T * k)] = v[k];
+        __syncthreads();
+        cpx<R>* dst = dst0 + g * NL;
+        for (int idx = threadIdx.x; idx < N * NL; idx += NL * T) {
+            const int q = idx / NL, l = idx % NL;
+            const int f = (q - half) & (Np - 1);
+            dst[(size_t)q * Np + l] = buf[l * LP + lpad(f)];
+        }
     }
 }
 
@@ -852,41 +903,73 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
     }
 }
 
-// degrid pass A': for each layer t and block of columns r: read intermediate
-// column [t][:][r] (transposed), zero-pad along q, FFT along q -> stack row [t][r][s].
+// degrid pass A': for each layer t and column r: read intermediate column
+// [t][:][r] (transposed), zero-pad along q, FFT along q -> stack row [t][r][s].
+// One block per layer and row of tiles (kTileR columns, taken NL at a time);
+// the next NL columns are loaded while the current ones are transformed.  Only
+// marked tiles are stored (the gather reads no other); a row of tiles with none
+// marked is skipped.
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
-    k_degrid_fft_a(const cpx<R>* __restrict__ inter, const cpx<R>* __restrict__ tw, cpx<R>* __restrict__ stack,
-                   int N, int n_layers) {
+    k_degrid_fft_a(const cpx<R>* __restrict__ inter, const uint8_t* __restrict__ occ, const cpx<R>* __restrict__ tw,
+                   cpx<R>* __restrict__ stack, int N, int n_layers, int nbr) {
     using C = FftCfg<R, LOGN>;
-    constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size;
+    constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size, NG = kTileR / NL;
+    constexpr int NT = NL * T;
+    static_assert(kTileR % NL == 0, "a row of tiles is a whole number of line groups");
     __shared__ cpx<R> buf[NL * LP];
-    const int blocks_per_plane = Np / NL;
+    const int rows = Np / kTileR;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int t = lb / blocks_per_plane, r0 = (lb % blocks_per_plane) * NL;
+    const int t = lb / rows, rt = lb % rows;
     const int line = threadIdx.x / T, j = threadIdx.x % T;
     cpx<R>* lbuf = buf + line * LP;
+    const uint8_t* orow = occ + (size_t)(t / kTileT) * (Np / kTileS) * nbr + rt;
+    bool on[16], any = false;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        on[k] = orow[(size_t)((j + T * k) / kTileS) * nbr] != 0;
+        any = any || on[k];
+    }
+    if (!__syncthreads_or(any)) return;
     const int half = N / 2;
-    // zero the padding bins, then the transposed load of the N image rows
-    for (int idx = threadIdx.x; idx < (Np - N) * NL; idx += NL * T) {
-        const int l = idx % NL, e = idx / NL;                 // e-th bin outside the image
-        const int f = (N - half + e) & (Np - 1);              // bins N/2 .. Np - N/2 - 1
-        buf[l * LP + lpad(f)] = cpx<R>{R(0), R(0)};
-    }
-    const cpx<R>* src = inter + (size_t)t * N * Np + r0;
-    for (int idx = threadIdx.x; idx < N * NL; idx += NL * T) {
-        const int q = idx / NL, l = idx % NL;
-        const int f = (q - half) & (Np - 1);
-        buf[l * LP + lpad(f)] = src[(size_t)q * Np + l];
-    }
-    __syncthreads();
-    cpx<R> v[16];
+    const cpx<R>* src0 = inter + (size_t)t * N * Np + rt * kTileR;
+    // element i of this thread: idx = threadIdx.x + NT i < N NL, q = idx / NL, l = idx % NL
+    auto load = [&](int g, cpx<R> (&u)[16]) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = lbuf[lpad(j + T * k)];
-    fft_line<R, LOGN, -1>(v, lbuf, tw, j);
-    cpx<R>* dst = stack + ((size_t)t * Np + (r0 + line)) * Np;
+        for (int i = 0; i < 16; ++i) {
+            const int idx = threadIdx.x + NT * i;
+            if (idx < N * NL) u[i] = src0[(size_t)(idx / NL) * Np + g * NL + idx % NL];
+        }
+    };
+    cpx<R> nx[16];
+    load(0, nx);
+    for (int g = 0; g < NG; ++g) {
+        __syncthreads();                        // the previous group is done with buf
+        // zero the padding bins, place the image rows at their bins
+        for (int idx = threadIdx.x; idx < (Np - N) * NL; idx += NT) {
+            const int l = idx % NL, e = idx / NL;                 // e-th bin outside the image
+            const int f = (N - half + e) & (Np - 1);              // bins N/2 .. Np - N/2 - 1
+            buf[l * LP + lpad(f)] = cpx<R>{R(0), R(0)};
+        }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) dst[j + T * k] = v[k];
+        for (int i = 0; i < 16; ++i) {
+            const int idx = threadIdx.x + NT * i;
+            if (idx < N * NL) {
+                const int q = idx / NL, l = idx % NL;
+                buf[l * LP + lpad((q - half) & (Np - 1))] = nx[i];
+            }
+        }
+        __syncthreads();
+        if (g + 1 < NG) load(g + 1, nx);
+        cpx<R> v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = lbuf[lpad(j + T * k)];
+        fft_line<R, LOGN, -1>(v, lbuf, tw, j);
+        cpx<R>* dst = stack + ((size_t)t * Np + (rt * kTileR + g * NL + line)) * Np;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (on[k]) dst[j + T * k] = v[k];
+    }
 }
 
 // --------------------------------------------------------------- plan tables --

@@ -86,7 +86,7 @@ struct wsg_plan {
 namespace {
 
 struct Layout {
-    size_t stack, inter, rec, rec2, count, start, cursor, bsums, cls, skipped, total;
+    size_t stack, inter, rec, rec2, count, start, cursor, bsums, cls, occ, skipped, total;
     int nbins, nscan;
 };
 
@@ -107,6 +107,7 @@ Layout layout_of(const wsg_plan* p, int prec, int64_t M) {
     L.cursor = off;  off += al256(size_t(L.nbins) * 4);
     L.bsums = off;   off += al256(size_t(L.nscan) * 4);
     L.cls = off;     off += al256(size_t(L.nbins) * 8 * 4);
+    L.occ = off;     off += al256(size_t(L.nbins));
     L.stack = off;   off += al256(nl * Np * Np * cs);
     L.inter = off;   off += al256(nl * N * Np * cs);
     L.rec = off;     off += al256(size_t(M) * rs);
@@ -151,9 +152,10 @@ void scan(const uint32_t* count, uint32_t* start, uint32_t* bsums, int n, hipStr
 
 template <typename R, int W>
 void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
-                    const DevParams& P, const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
+                    const uint8_t* occ, const DevParams& P, const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
     if (grid)
-        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, P, coef, stack);
+        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, occ, P, coef,
+                           stack);
     else
         hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, P, coef,
                            (const cpx<R>*)stack, vis);
@@ -161,10 +163,10 @@ void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* s
 
 template <typename R>
 void launch_tiles(bool grid, int W, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
-                  const DevParams& P, const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
+                  const uint8_t* occ, const DevParams& P, const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
     switch (W) {
 #define WSG_W(w) \
-    case w: launch_tiles_w<R, w>(grid, nblocks, rec, start, cls, P, coef, stack, vis, s); break;
+    case w: launch_tiles_w<R, w>(grid, nblocks, rec, start, cls, occ, P, coef, stack, vis, s); break;
         WSG_W(1) WSG_W(2) WSG_W(3) WSG_W(4) WSG_W(5) WSG_W(6) WSG_W(7) WSG_W(8)
         WSG_W(9) WSG_W(10) WSG_W(11) WSG_W(12) WSG_W(13) WSG_W(14) WSG_W(15) WSG_W(16)
 #undef WSG_W
@@ -173,16 +175,16 @@ void launch_tiles(bool grid, int W, int nblocks, const Rec<R>* rec, const uint32
 }
 
 template <typename R, int LOGN>
-void launch_fft_n(bool grid, const DevParams& P, cpx<R>* stack, cpx<R>* inter, const cpx<R>* tw, const R* corr,
-                  const R* image, R* dirty, hipStream_t s) {
+void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, cpx<R>* stack, cpx<R>* inter,
+                  const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
     using C = FftCfg<R, LOGN>;
-    const unsigned grid_a = unsigned(P.n_layers) * unsigned(C::N / C::kNLt);
+    const unsigned grid_a = unsigned(P.n_layers) * unsigned(C::N / kTileR);
     const unsigned grid_b = unsigned((P.N + C::kNLr - 1) / C::kNLr);
     if (grid) {
         {
             StageMark mark(s, 2);
             hipLaunchKernelGGL((k_grid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
-                               (const cpx<R>*)stack, inter, tw, P.N, P.n_layers);
+                               (const cpx<R>*)stack, occ, inter, tw, P.N, P.n_layers, P.nbr);
         }
         StageMark mark(s, 3);
         hipLaunchKernelGGL((k_grid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
@@ -195,16 +197,16 @@ void launch_fft_n(bool grid, const DevParams& P, cpx<R>* stack, cpx<R>* inter, c
         }
         StageMark mark(s, 6);
         hipLaunchKernelGGL((k_degrid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
-                           (const cpx<R>*)inter, tw, stack, P.N, P.n_layers);
+                           (const cpx<R>*)inter, occ, tw, stack, P.N, P.n_layers, P.nbr);
     }
 }
 
 template <typename R>
-void launch_fft(bool grid, int log2n, const DevParams& P, cpx<R>* stack, cpx<R>* inter, const cpx<R>* tw,
-                const R* corr, const R* image, R* dirty, hipStream_t s) {
+void launch_fft(bool grid, int log2n, const DevParams& P, const uint8_t* occ, cpx<R>* stack, cpx<R>* inter,
+                const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
     switch (log2n) {
 #define WSG_N(n) \
-    case n: launch_fft_n<R, n>(grid, P, stack, inter, tw, corr, image, dirty, s); break;
+    case n: launch_fft_n<R, n>(grid, P, occ, stack, inter, tw, corr, image, dirty, s); break;
         WSG_N(6) WSG_N(7) WSG_N(8) WSG_N(9) WSG_N(10) WSG_N(11) WSG_N(12) WSG_N(13)
 #undef WSG_N
         default: break;
@@ -245,6 +247,7 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
     auto* cursor = reinterpret_cast<uint32_t*>(w + L.cursor);
     auto* bsums = reinterpret_cast<uint32_t*>(w + L.bsums);
     auto* cls = reinterpret_cast<uint32_t*>(w + L.cls);
+    auto* occ = reinterpret_cast<uint8_t*>(w + L.occ);
     auto* skipped = reinterpret_cast<uint32_t*>(w + L.skipped);
     const bool f64 = sizeof(R) == 8;
     const R* coef = f64 ? reinterpret_cast<const R*>(plan->poly64) : reinterpret_cast<const R*>(plan->poly32);
@@ -271,18 +274,20 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
             hipLaunchKernelGGL(k_bin_local_sort<R>, dim3(L.nbins), dim3(256), 0, s, (const Rec<R>*)rec_bin, rec,
                                (const uint32_t*)start, cls, P);
         }
+        hipLaunchKernelGGL(k_tile_occupancy, dim3((L.nbins + 255) / 256), dim3(256), 0, s, (const uint32_t*)start, P,
+                           occ);
     }
     if (grid) {
         {
             StageMark mark(s, 1);
-            launch_tiles<R>(true, P.W, L.nbins, rec, start, cls, P, coef, stack, nullptr, s);
+            launch_tiles<R>(true, P.W, L.nbins, rec, start, cls, occ, P, coef, stack, nullptr, s);
         }
-        launch_fft<R>(true, plan->log2_np, P, stack, inter, tw, corr, nullptr, static_cast<R*>(out), s);
+        launch_fft<R>(true, plan->log2_np, P, occ, stack, inter, tw, corr, nullptr, static_cast<R*>(out), s);
     } else {
-        launch_fft<R>(false, plan->log2_np, P, stack, inter, tw, corr, static_cast<const R*>(in), nullptr, s);
+        launch_fft<R>(false, plan->log2_np, P, occ, stack, inter, tw, corr, static_cast<const R*>(in), nullptr, s);
         StageMark mark(s, 7);
         fill<R>(static_cast<R*>(out), size_t(2 * M), R(0), s);
-        if (M > 0) launch_tiles<R>(false, P.W, L.nbins, rec, start, cls, P, coef, stack, static_cast<R*>(out), s);
+        if (M > 0) launch_tiles<R>(false, P.W, L.nbins, rec, start, cls, occ, P, coef, stack, static_cast<R*>(out), s);
     }
     WSG_HIP(hipGetLastError());
     return WSG_OK;
