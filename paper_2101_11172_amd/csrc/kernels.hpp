@@ -55,9 +55,10 @@ __device__ __forceinline__ bool vis_coords(const double* __restrict__ uvw, long 
     axis_support(up, P.W, c.nu_u, fu);
     axis_support(vp, P.W, c.nu_v, fv);
     axis_support(wp, P.W, c.nu_w, ft);
-    long long Np = P.Np;
-    c.ru = int(((fu % Np) + Np) % Np);
-    c.rv = int(((fv % Np) + Np) % Np);
+    // N' is a power of two: the mask is the non-negative residue modulo N'
+    const long long mask = P.Np - 1;
+    c.ru = int(fu & mask);
+    c.rv = int(fv & mask);
     long long it = ft - P.t_lo;
     if (it < 0 || it > P.n_layers - P.W) return false;
     c.rt = int(it);
@@ -69,16 +70,76 @@ __device__ __forceinline__ int bin_of(const VisCoords& c, const DevParams& P) {
     return (c.rt / kTileT * P.nbs + c.rv / kTileS) * P.nbr + c.ru / kTileR;
 }
 
-__global__ void k_bin_count(const double* __restrict__ uvw, long long M, DevParams P,
-                            uint32_t* __restrict__ count, uint32_t* __restrict__ skipped) {
-    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M) return;
-    VisCoords c;
-    if (!vis_coords(uvw, k, P, c)) {
-        atomicAdd(skipped, 1u);
-        return;
+// Bin counts and cursors are updated with device-scope atomics, whose cost is
+// per operation.  A block therefore takes a chunk of kAggChunk consecutive
+// visibilities (a run of time steps of every baseline, whose tracks stay in few
+// bins) and aggregates them per bin in an LDS table (open addressing, bounded
+// probing) before one global update per distinct bin; a visibility whose bin
+// finds no table slot updates the global counter directly.
+constexpr int kAggThreads = 1024;
+constexpr int kAggPer = 32;
+constexpr int kAggChunk = kAggThreads * kAggPer;
+constexpr int kAggSlots = 4096;
+constexpr int kAggProbes = 32;
+
+struct AggTable {
+    int key[kAggSlots];
+    uint32_t cnt[kAggSlots];
+    uint32_t base[kAggSlots];
+    uint32_t skipped;
+};
+
+__device__ __forceinline__ void agg_init(AggTable& T) {
+    for (int i = threadIdx.x; i < kAggSlots; i += blockDim.x) {
+        T.key[i] = -1;
+        T.cnt[i] = 0u;
     }
-    atomicAdd(&count[bin_of(c, P)], 1u);
+    if (threadIdx.x == 0) T.skipped = 0u;
+}
+
+// slot of key (inserted if absent), or -1 when the probe sequence is full
+__device__ __forceinline__ int agg_slot(AggTable& T, int key) {
+    int h = int((uint32_t(key) * 2654435761u) >> (32 - 12)) & (kAggSlots - 1);
+    for (int p = 0; p < kAggProbes; ++p) {
+        const int k = T.key[h];
+        if (k == key) return h;
+        if (k == -1) {
+            const int old = atomicCAS(&T.key[h], -1, key);
+            if (old == -1 || old == key) return h;
+        }
+        h = (h + 1) & (kAggSlots - 1);
+    }
+    return -1;
+}
+
+__global__ void __launch_bounds__(kAggThreads) k_bin_count(const double* __restrict__ uvw, long long M, DevParams P,
+                                                           uint32_t* __restrict__ count,
+                                                           uint32_t* __restrict__ skipped) {
+    __shared__ AggTable T;
+    agg_init(T);
+    __syncthreads();
+    const long long k0 = (long long)blockIdx.x * kAggChunk;
+    uint32_t my_skipped = 0;
+    for (int i = 0; i < kAggPer; ++i) {
+        const long long k = k0 + (long long)i * kAggThreads + threadIdx.x;
+        if (k >= M) break;
+        VisCoords c;
+        if (!vis_coords(uvw, k, P, c)) {
+            ++my_skipped;
+            continue;
+        }
+        const int b = bin_of(c, P);
+        const int sl = agg_slot(T, b);
+        if (sl >= 0)
+            atomicAdd(&T.cnt[sl], 1u);
+        else
+            atomicAdd(&count[b], 1u);
+    }
+    if (my_skipped) atomicAdd(&T.skipped, my_skipped);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAggSlots; i += kAggThreads)
+        if (T.key[i] >= 0) atomicAdd(&count[T.key[i]], T.cnt[i]);
+    if (threadIdx.x == 0 && T.skipped) atomicAdd(skipped, T.skipped);
 }
 
 // Exclusive scan of n uint32 counts: per-block scan (1024 items per block of
@@ -153,36 +214,62 @@ __global__ void k_scan_add(uint32_t* __restrict__ out, int n, const uint32_t* __
 // grid: v = V exp(+i 2 pi w (n0 - 1)) with n0 - 1 = -z0 n_scale (eq. n_params),
 // V conjugated for a folded visibility.  degrid: v = exp(-i 2 pi w (n0 - 1)).
 template <typename R, bool GRID>
-__global__ void k_bin_scatter(const double* __restrict__ uvw, const cpx<R>* __restrict__ vis, long long M,
-                              DevParams P, const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
-                              Rec<R>* __restrict__ rec) {
-    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M) return;
-    VisCoords c;
-    if (!vis_coords(uvw, k, P, c)) return;
-    const int b = bin_of(c, P);
-    const uint32_t pos = start[b] + atomicAdd(&cursor[b], 1u);
-    Rec<R> r;
-    r.ruv = uint32_t(c.ru) | (uint32_t(c.rv) << 16);
-    r.rt = uint32_t(c.rt);
-    r.nu[0] = R(c.nu_u);
-    r.nu[1] = R(c.nu_v);
-    r.nu[2] = R(c.nu_w);
-    double turns = c.w * (-P.z0 * P.nscale);     // w (n0 - 1)
-    double s, co;
-    phase_turns(GRID ? turns : -turns, &s, &co);
-    if (GRID) {
-        cpx<R> V = vis[k];
-        double vx = double(V.x), vy = c.folded ? -double(V.y) : double(V.y);
-        r.v[0] = R(vx * co - vy * s);
-        r.v[1] = R(vx * s + vy * co);
-        r.idx = 0;
-    } else {
-        r.v[0] = R(co);
-        r.v[1] = R(s);
-        r.idx = uint32_t(k) | (c.folded ? 0x80000000u : 0u);
+__global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __restrict__ uvw,
+                                                             const cpx<R>* __restrict__ vis, long long M, DevParams P,
+                                                             const uint32_t* __restrict__ start,
+                                                             uint32_t* __restrict__ cursor, Rec<R>* __restrict__ rec) {
+    __shared__ AggTable T;
+    agg_init(T);
+    __syncthreads();
+    const long long k0 = (long long)blockIdx.x * kAggChunk;
+    // pass 1: rank of each visibility among this block's visibilities of its bin
+    uint32_t tag[kAggPer];             // slot << 16 | rank; 0xffffffff: direct update
+#pragma unroll
+    for (int i = 0; i < kAggPer; ++i) {
+        tag[i] = 0xffffffffu;
+        const long long k = k0 + (long long)i * kAggThreads + threadIdx.x;
+        VisCoords c;
+        if (k < M && vis_coords(uvw, k, P, c)) {
+            const int sl = agg_slot(T, bin_of(c, P));
+            if (sl >= 0) tag[i] = (uint32_t(sl) << 16) | atomicAdd(&T.cnt[sl], 1u);
+        }
     }
-    rec[pos] = r;
+    __syncthreads();
+    // one reservation per distinct bin of the block
+    for (int i = threadIdx.x; i < kAggSlots; i += kAggThreads)
+        if (T.key[i] >= 0) T.base[i] = atomicAdd(&cursor[T.key[i]], T.cnt[i]);
+    __syncthreads();
+    // pass 2: write the records
+#pragma unroll
+    for (int i = 0; i < kAggPer; ++i) {
+        const long long k = k0 + (long long)i * kAggThreads + threadIdx.x;
+        VisCoords c;
+        if (!(k < M && vis_coords(uvw, k, P, c))) continue;
+        const int b = bin_of(c, P);
+        const uint32_t off = tag[i] != 0xffffffffu ? T.base[tag[i] >> 16] + (tag[i] & 0xffffu)
+                                                   : atomicAdd(&cursor[b], 1u);
+        Rec<R> r;
+        r.ruv = uint32_t(c.ru) | (uint32_t(c.rv) << 16);
+        r.rt = uint32_t(c.rt);
+        r.nu[0] = R(c.nu_u);
+        r.nu[1] = R(c.nu_v);
+        r.nu[2] = R(c.nu_w);
+        double turns = c.w * (-P.z0 * P.nscale);     // w (n0 - 1)
+        double sn, co;
+        phase_turns(GRID ? turns : -turns, &sn, &co);
+        if (GRID) {
+            cpx<R> V = vis[k];
+            double vx = double(V.x), vy = c.folded ? -double(V.y) : double(V.y);
+            r.v[0] = R(vx * co - vy * sn);
+            r.v[1] = R(vx * sn + vy * co);
+            r.idx = 0;
+        } else {
+            r.v[0] = R(co);
+            r.v[1] = R(sn);
+            r.idx = uint32_t(k) | (c.folded ? 0x80000000u : 0u);
+        }
+        rec[start[b] + off] = r;
+    }
 }
 
 // Second-level sort and touch classes.  With B = 17 - W, a record whose first

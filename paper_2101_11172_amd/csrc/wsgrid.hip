@@ -259,17 +259,18 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
         fill<uint32_t>(count, size_t(L.nbins), 0u, s);
         fill<uint32_t>(cursor, size_t(L.nbins), 0u, s);
         fill<uint32_t>(skipped, 1, 0u, s);
-        const unsigned vblocks = unsigned((M + 255) / 256);
+        const unsigned vblocks = unsigned((M + kAggChunk - 1) / kAggChunk);
         if (M > 0)
-            hipLaunchKernelGGL(k_bin_count, dim3(vblocks), dim3(256), 0, s, uvw, (long long)M, P, count, skipped);
+            hipLaunchKernelGGL(k_bin_count, dim3(vblocks), dim3(kAggThreads), 0, s, uvw, (long long)M, P, count,
+                               skipped);
         scan(count, start, bsums, L.nbins, s);
         if (M > 0) {
             if (grid)
-                hipLaunchKernelGGL((k_bin_scatter<R, true>), dim3(vblocks), dim3(256), 0, s, uvw,
+                hipLaunchKernelGGL((k_bin_scatter<R, true>), dim3(vblocks), dim3(kAggThreads), 0, s, uvw,
                                    static_cast<const cpx<R>*>(in), (long long)M, P, (const uint32_t*)start, cursor,
                                    rec_bin);
             else
-                hipLaunchKernelGGL((k_bin_scatter<R, false>), dim3(vblocks), dim3(256), 0, s, uvw,
+                hipLaunchKernelGGL((k_bin_scatter<R, false>), dim3(vblocks), dim3(kAggThreads), 0, s, uvw,
                                    (const cpx<R>*)nullptr, (long long)M, P, (const uint32_t*)start, cursor, rec_bin);
             hipLaunchKernelGGL(k_bin_local_sort<R>, dim3(L.nbins), dim3(256), 0, s, (const Rec<R>*)rec_bin, rec,
                                (const uint32_t*)start, cls, P);
