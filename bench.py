@@ -31,22 +31,63 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool) -> float:
+def workload_stats(uvw, N: int, L: float, W: int, x0: float, wmax: float, Np: int, nl: int, t_lo: int,
+                   n_scale: float) -> dict:
+    """Counts that fix the algorithmic bytes of the sparse stack (host numpy, no oracle).
+
+    A visibility's first support index per axis is floor(xi + W/2) - W + 1 with
+    xi = (l_max / x0) u, (l_max / x0) v, n_scale w after the Hermitian fold;
+    bins are 16^3 tiles of the stack.  A tile is occupied when its own bin or
+    one of the seven bins one tile back holds a visibility (what the library
+    writes and reads); a visibility visits 1 + [first index in tile >= 17 - W]
+    tiles per axis.
+    """
+    import numpy as np
+
+    u, v, w = (uvw[:, i].astype(np.float64) for i in range(3))
+    neg = w < 0
+    u, v, w = np.where(neg, -u, u), np.where(neg, -v, v), np.abs(w)
+    umul = (L / 2) / x0
+    fu = (np.floor(umul * u + W / 2).astype(np.int64) - W + 1) % Np
+    fv = (np.floor(umul * v + W / 2).astype(np.int64) - W + 1) % Np
+    ft = np.floor(n_scale * w + W / 2).astype(np.int64) - W + 1 - t_lo
+    T = 16
+    nb, nbt = Np // T, (nl + T - 1) // T
+    cnt = np.bincount((ft // T * nb + fv // T) * nb + fu // T, minlength=nbt * nb * nb).reshape(nbt, nb, nb)
+    B = 17 - W
+    visits = int(np.sum((1 + (ft % T >= B)) * (1 + (fu % T >= B)) * (1 + (fv % T >= B))))
+    reach = cnt > 0
+    reach = reach | np.roll(reach, 1, axis=2)          # one tile back along u (periodic)
+    reach = reach | np.roll(reach, 1, axis=1)          # and along v
+    occ = reach.copy()
+    occ[1:] |= reach[:-1]                               # and along t (not periodic)
+    cells_per_t = np.array([min(T, nl - T * i) for i in range(nbt)]) * T * T
+    occ_cells = int(np.sum(occ.sum(axis=(1, 2)) * cells_per_t))
+    rows = occ.any(axis=1)                              # [t tile][u tile]: any tile along v
+    row_lines = int(np.sum(rows.sum(axis=1) * np.array([min(T, nl - T * i) for i in range(nbt)]) * T))
+    return {"tiles_occupied": int(occ.sum()), "tiles": int(occ.size), "occupied_cells": occ_cells,
+            "tile_visits": visits, "nonempty_lines": row_lines, "lines": nl * Np}
+
+
+def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict) -> float:
     """Algorithmic HBM bytes of one launch of a stage (what the stage must move)."""
     b = 16 if f64 else 8            # complex
     r = 8 if f64 else 4             # real
     rec = 56 if f64 else 32         # binned record
-    stack = nl * Np * Np * b
     inter = nl * N * Np * b
+    tiles = ws["occupied_cells"] * b                    # occupied tiles of the stack
+    inter_rows = ws["nonempty_lines"] * N * b           # intermediate lines that meet an occupied tile
+    sort = 2 * M * rec                                  # per-bin sort: records in and out
     return {
-        "grid_bin": M * (2 * 24 + b + rec),          # uvw read twice, vis, records written
-        "grid_tiles": M * rec + stack,                # records in, stack out
-        "grid_fft_v": stack + inter,                  # stack in, intermediate out
-        "grid_fft_u": inter + 2 * N * N * r,          # intermediate, correction in, map out
-        "degrid_bin": M * (2 * 24 + rec),
-        "degrid_fft_p": 2 * N * N * r + inter,        # image, correction in, intermediate out
-        "degrid_fft_q": inter + stack,
-        "degrid_tiles": stack + M * rec + M * b,      # stack, records in, visibilities out
+        "grid_bin": M * (2 * 24 + b + rec) + sort,      # uvw read twice, vis, records written, sorted
+        "grid_tiles": ws["tile_visits"] * rec + tiles,  # records in (once per tile reached), tiles out
+        "grid_fft_v": tiles + inter,                    # occupied tiles in, intermediate out
+        "grid_fft_u": inter + 2 * N * N * r,            # intermediate, correction in, map out
+        "degrid_bin": M * (2 * 24 + rec) + sort,
+        "degrid_fft_p": 2 * N * N * r + inter,          # image, correction in, intermediate out
+        "degrid_fft_q": inter_rows + tiles,             # intermediate rows in, occupied tiles out
+        # tiles and records in, one part out per visit; then per record its parts in, the visibility out
+        "degrid_tiles": tiles + ws["tile_visits"] * (rec + b) + M * rec + ws["tile_visits"] * b + M * b,
     }[st]
 
 
@@ -143,13 +184,13 @@ def cpu_baseline(w: dict, n_sample: int) -> dict:
     }
 
 
-def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int) -> dict:
+def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int, ws: dict) -> dict:
     tab = {}
     for name, (ms, n) in stages.items():
         if n == 0:
             continue
         per = ms / n
-        nbytes = stage_bytes(name, M, N, Np, nl, f64)
+        nbytes = stage_bytes(name, M, N, Np, nl, f64, ws)
         tab[name] = {"ms": per, "launches": n, "alg_bytes": nbytes, "alg_GBps": nbytes / (per * 1e-3) / 1e9}
     return tab
 
@@ -199,9 +240,9 @@ def main() -> int:
         n = int(args.copy_gb * 1e9) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)            # one elementwise kernel: reads and writes 4n bytes
         torch.cuda.synchronize()
-        log(f"calibration copy: {4 * n} bytes read, {4 * n} bytes written")
+        log(f"calibration kernel: {4 * n} bytes read, {4 * n} bytes written")
         del src, dst
     log("generating the wide-field workload")
     w = inputs.workload("widefield", n_dumps=args.dumps, vis_dtype=np.complex64)
@@ -211,6 +252,8 @@ def main() -> int:
     info = plan.info
     Np, nl = info["Nprime"], info["n_layers"]
     log(f"M={M} N={N} N'={Np} layers={nl} E={info['E']:.3e}")
+    ws = workload_stats(w["uvw"], N, L, W, x0, wmax, Np, nl, info["t_lo"], info["n_scale"])
+    log(f"occupied tiles {ws['tiles_occupied']}/{ws['tiles']}, tile visits {ws['tile_visits']}")
     uvw = torch.from_numpy(w["uvw"]).to(dev)
     vis32 = torch.from_numpy(w["vis"]).to(dev)
     img32 = torch.from_numpy(inputs.random_image(N, 5).astype(np.float32)).to(dev)
@@ -228,7 +271,7 @@ def main() -> int:
     ms32, stages32 = timed(step32, args.steps)
     log(f"fp32: {ms32:.3f} ms/step, {M / (ms32 * 1e-3):.4e} vis/s")
     skipped = plan.skipped(wsgrid.WSG_F32)
-    tab32 = stage_table(stages32, False, M, N, Np, nl)
+    tab32 = stage_table(stages32, False, M, N, Np, nl, ws)
 
     fp64, acc = None, None
     if args.fp64_steps > 0:
@@ -244,7 +287,7 @@ def main() -> int:
         ms64, stages64 = timed(step64, args.fp64_steps)
         log(f"fp64: {ms64:.3f} ms/step, {M / (ms64 * 1e-3):.4e} vis/s")
         fp64 = {"value": M / (ms64 * 1e-3), "ms_per_step": ms64,
-                "stages": stage_table(stages64, True, M, N, Np, nl)}
+                "stages": stage_table(stages64, True, M, N, Np, nl, ws)}
 
         def relrms(a, b):
             return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
@@ -257,7 +300,7 @@ def main() -> int:
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic_for(dom, "f32"),
                 "alg_bytes_per_launch": d["alg_bytes"], "ms_per_launch": d["ms"]}
-    total_alg = sum(stage_bytes(s, M, N, Np, nl, False) for s in tab32)
+    total_alg = sum(stage_bytes(s, M, N, Np, nl, False, ws) for s in tab32)
     result = {
         "metric": "visibilities/s grid+degrid at W=7,x0=0.25, FP32 vs FP64, at <=1e-6 DFT error",
         "value": M / (ms32 * 1e-3),
@@ -280,6 +323,7 @@ def main() -> int:
         "fp64": fp64,
         "fp32_vs_fp64_rel_rms": acc,
         "stages": tab32,
+        "stack_occupancy": ws,
         "skipped": skipped,
     }
     if not args.no_cpu:

@@ -394,6 +394,7 @@ struct KernelDegree {
 struct TileSegs {
     uint32_t lo[64];
     uint32_t off[65];
+    uint32_t nbr[64];     // neighbour set of the range's bin: it | ir << 1 | is << 2
     int n;
 };
 
@@ -431,6 +432,7 @@ __device__ __forceinline__ void tile_segments(const uint32_t* __restrict__ start
         const int g = __popcll(fm & ((1ull << lane) - 1ull));
         sg.lo[g] = lo;
         sg.off[g] = inc - len;
+        sg.nbr[g] = uint32_t(it | (ir << 1) | (is << 2));
     }
     if (lane == 63) {
         const int n = __popcll(fm);
@@ -439,10 +441,11 @@ __device__ __forceinline__ void tile_segments(const uint32_t* __restrict__ start
     }
 }
 
-// record array index of virtual position v
-__device__ __forceinline__ uint32_t seg_index(const TileSegs& sg, int n, uint32_t v) {
+// record array index of virtual position v (and, optionally, its range)
+__device__ __forceinline__ uint32_t seg_index(const TileSegs& sg, int n, uint32_t v, int* range = nullptr) {
     int g = 0;
     for (int k = 1; k < n; ++k) g += sg.off[k] <= v ? 1 : 0;
+    if (range) *range = g;
     return sg.lo[g] + (v - sg.off[g]);
 }
 
@@ -722,7 +725,8 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
                                                       const uint32_t* __restrict__ start,
                                                       const uint32_t* __restrict__ cls, DevParams P,
                                                       const R* __restrict__ coef_g,
-                                                      const cpx<R>* __restrict__ stack, R* __restrict__ vis) {
+                                                      const cpx<R>* __restrict__ stack, cpx<R>* __restrict__ part,
+                                                      size_t part_stride) {
     using G = GatherCfg<R, W>;
     constexpr int D = KernelDegree<R>::value;
     constexpr int WB = 64;
@@ -747,7 +751,13 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     const uint32_t q0 = min(total, quarter * uint32_t(wv)), q1 = min(total, q0 + quarter);
 
     Rec<R> nxt;
-    if (q0 + uint32_t(lane) < q1) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(lane))];
+    uint32_t nxt_p = 0, nxt_m = 0;
+    int g_ = 0;
+    if (q0 + uint32_t(lane) < q1) {
+        nxt_p = seg_index(sg, nseg, q0 + uint32_t(lane), &g_);
+        nxt_m = sg.nbr[g_];
+        nxt = rec[nxt_p];
+    }
     for (int i = tid; i < G::kLen; i += 256) {
         const int c = i - G::kGuard;
         cpx<R> q{R(0), R(0)};
@@ -762,8 +772,13 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     for (uint32_t base = q0; base < q1; base += WB) {
         const bool live = base + uint32_t(lane) < q1;
         const Rec<R> r = nxt;
+        const uint32_t p = nxt_p, m = nxt_m;
         const uint32_t vn = base + WB + uint32_t(lane);
-        if (vn < q1) nxt = rec[seg_index(sg, nseg, vn)];
+        if (vn < q1) {
+            nxt_p = seg_index(sg, nseg, vn, &g_);
+            nxt_m = sg.nbr[g_];
+            nxt = rec[nxt_p];
+        }
         if (!live) continue;
 
         const int dr = wrap_offset(int(r.ruv & 0xffffu), r0, P.Np);
@@ -799,19 +814,46 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
             sx += ax * wt[a];
             sy += ay * wt[a];
         }
-        // phase exp(-i 2 pi w (n0 - 1)), conjugate for a folded visibility
-        R ox = sx * r.v[0] - sy * r.v[1], oy = sx * r.v[1] + sy * r.v[0];
-        if (r.idx & 0x80000000u) oy = -oy;
-        const size_t k = r.idx & 0x7fffffffu;
-        atomicAdd(&vis[2 * k], ox);
-        atomicAdd(&vis[2 * k + 1], oy);
+        // this tile's part of record p, in the slot of the tile's offset from
+        // the record's own bin (no two tiles share a slot)
+        part[(size_t)m * part_stride + p] = cpx<R>{sx, sy};
     }
+}
+
+// Sum of each record's parts over the tiles it reaches (slot m is written by
+// the tile one step forward along the axes of m, present when the record's
+// touch class contains m), times the phase exp(-i 2 pi w (n0 - 1)), conjugated
+// for a folded visibility, stored to its visibility.
+template <typename R>
+__global__ void k_degrid_finish(const Rec<R>* __restrict__ rec, const uint32_t* __restrict__ n_rec,
+                                const cpx<R>* __restrict__ part, size_t part_stride, int W,
+                                cpx<R>* __restrict__ vis) {
+    const size_t p = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= *n_rec) return;
+    const Rec<R> r = rec[p];
+    const int B = 17 - W;
+    const int c = class_of(int(r.rt) & (kTileT - 1), int(r.ruv & 0xffffu) & (kTileR - 1),
+                           int(r.ruv >> 16) & (kTileS - 1), B);
+    R sx = R(0), sy = R(0);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        if ((c & m) == m) {
+            const cpx<R> q = part[(size_t)m * part_stride + p];
+            sx += q.x;
+            sy += q.y;
+        }
+    }
+    R ox = sx * r.v[0] - sy * r.v[1], oy = sx * r.v[1] + sy * r.v[0];
+    if (r.idx & 0x80000000u) oy = -oy;
+    vis[r.idx & 0x7fffffffu] = cpx<R>{ox, oy};
 }
 
 // --------------------------------------------------------------- FFT passes --
 //
-// Stack layout [t][r][s] (s fastest); intermediate layout [t][q][r] (r fastest),
-// q the image row.  Image rows j <-> q and columns i <-> p.  The FFT output bin
+// Stack layout [t][r][s] (s fastest).  Intermediate: grid [t][q][r] (r fastest),
+// degrid [t][r][q] (q fastest); q is the image row.  Each direction's transpose
+// is done on its write side, where narrow runs are merged in L2, so that the
+// reads are whole lines.  Image rows j <-> q and columns i <-> p.  The FFT output bin
 // f of a line maps to image index (f + N/2) mod N' and is kept when below N
 // (Algorithm 5 step 3c); the degrid input places image index p at bin
 // (p - N/2) mod N' (zero padding, Algorithm 6 step 3b).
@@ -944,17 +986,21 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 }
 
 // degrid pass B': for each image row q and layer t: f h_x h_y h_z exp(-i 2 pi t z)
-// zero-padded along p, FFT along p -> intermediate [t][q][r] (Algorithm 6 steps 2-3).
+// zero-padded along p, FFT along p -> intermediate [t][r][q] (Algorithm 6 steps
+// 2-3).  A block takes NL consecutive rows; the transformed lines go through LDS
+// so that each frequency r is written as a run of NL consecutive q (the narrow
+// runs are on the write side, where the L2 merges them).
 template <typename R, int LOGN>
-__global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
+__global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_degrid_fft_b(const R* __restrict__ image, const R* __restrict__ corr, const cpx<R>* __restrict__ tw,
                    cpx<R>* __restrict__ inter, DevParams P) {
     using C = FftCfg<R, LOGN>;
-    constexpr int Np = C::N, T = C::T, NL = C::kNLr, LP = LinePad<Np>::size;
+    constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size;
     __shared__ cpx<R> buf[NL * LP];
     const int N = P.N, half = N / 2;
     const int line = threadIdx.x / T, j = threadIdx.x % T;
-    const int q = xcd_remap(blockIdx.x, gridDim.x) * NL + line;
+    const int q0 = xcd_remap(blockIdx.x, gridDim.x) * NL;
+    const int q = q0 + line;
     const bool row_ok = q < N;
     const int qq = row_ok ? q : 0;
     cpx<R>* lbuf = buf + line * LP;
@@ -972,6 +1018,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         const double nm1 = -r2 / (1.0 + sqrt(1.0 - r2));
         z[k] = nm1 / P.nscale + P.z0;
     }
+    const int nq = min(NL, N - q0);
     for (int t = 0; t < P.n_layers; ++t) {
         const double tl = double(t + P.t_lo);
         cpx<R> v[16];
@@ -982,27 +1029,30 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
             v[k] = cpx<R>{g[k] * c, g[k] * s};
         }
         fft_line<R, LOGN, -1>(v, lbuf, tw, j);
-        if (row_ok) {
-            cpx<R>* dst = inter + ((size_t)t * N + q) * Np;
+        __syncthreads();
 #pragma unroll
-            for (int k = 0; k < 16; ++k) dst[j + T * k] = v[k];
+        for (int k = 0; k < 16; ++k) lbuf[lpad(j + T * k)] = v[k];
+        __syncthreads();
+        cpx<R>* dst = inter + (size_t)t * Np * N + q0;
+        for (int idx = threadIdx.x; idx < Np * NL; idx += NL * T) {
+            const int r = idx / NL, l = idx % NL;
+            if (l < nq) dst[(size_t)r * N + l] = buf[l * LP + lpad(r)];
         }
     }
 }
 
-// degrid pass A': for each layer t and column r: read intermediate column
-// [t][:][r] (transposed), zero-pad along q, FFT along q -> stack row [t][r][s].
-// One block per layer and row of tiles (kTileR columns, taken NL at a time);
-// the next NL columns are loaded while the current ones are transformed.  Only
-// marked tiles are stored (the gather reads no other); a row of tiles with none
-// marked is skipped.
+// degrid pass A': for each layer t and frequency r: the intermediate line
+// [t][r][:] placed at its bins and zero-padded along q, FFT along q -> stack
+// row [t][r][s].  One block per layer and row of tiles (kTileR lines, taken NL
+// at a time); the next NL lines are loaded while the current ones are
+// transformed.  Only marked tiles are stored (the gather reads no other); a row
+// of tiles with none marked is skipped.
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_degrid_fft_a(const cpx<R>* __restrict__ inter, const uint8_t* __restrict__ occ, const cpx<R>* __restrict__ tw,
                    cpx<R>* __restrict__ stack, int N, int n_layers, int nbr) {
     using C = FftCfg<R, LOGN>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size, NG = kTileR / NL;
-    constexpr int NT = NL * T;
     static_assert(kTileR % NL == 0, "a row of tiles is a whole number of line groups");
     __shared__ cpx<R> buf[NL * LP];
     const int rows = Np / kTileR;
@@ -1019,38 +1069,23 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     }
     if (!__syncthreads_or(any)) return;
     const int half = N / 2;
-    const cpx<R>* src0 = inter + (size_t)t * N * Np + rt * kTileR;
-    // element i of this thread: idx = threadIdx.x + NT i < N NL, q = idx / NL, l = idx % NL
-    auto load = [&](int g, cpx<R> (&u)[16]) {
+    // thread j of a line holds bins f = j + T k; bin f carries image row
+    // q = (f + N/2) mod N' when that is below N, else zero padding
+    auto load = [&](int g, cpx<R> (&v)[16]) {
+        const cpx<R>* src = inter + ((size_t)t * Np + (rt * kTileR + g * NL + line)) * N;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int idx = threadIdx.x + NT * i;
-            if (idx < N * NL) u[i] = src0[(size_t)(idx / NL) * Np + g * NL + idx % NL];
+        for (int k = 0; k < 16; ++k) {
+            const int q = (j + T * k + half) & (Np - 1);
+            v[k] = q < N ? src[q] : cpx<R>{R(0), R(0)};
         }
     };
     cpx<R> nx[16];
     load(0, nx);
     for (int g = 0; g < NG; ++g) {
-        __syncthreads();                        // the previous group is done with buf
-        // zero the padding bins, place the image rows at their bins
-        for (int idx = threadIdx.x; idx < (Np - N) * NL; idx += NT) {
-            const int l = idx % NL, e = idx / NL;                 // e-th bin outside the image
-            const int f = (N - half + e) & (Np - 1);              // bins N/2 .. Np - N/2 - 1
-            buf[l * LP + lpad(f)] = cpx<R>{R(0), R(0)};
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int idx = threadIdx.x + NT * i;
-            if (idx < N * NL) {
-                const int q = idx / NL, l = idx % NL;
-                buf[l * LP + lpad((q - half) & (Np - 1))] = nx[i];
-            }
-        }
-        __syncthreads();
-        if (g + 1 < NG) load(g + 1, nx);
         cpx<R> v[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = lbuf[lpad(j + T * k)];
+        for (int k = 0; k < 16; ++k) v[k] = nx[k];
+        if (g + 1 < NG) load(g + 1, nx);
         fft_line<R, LOGN, -1>(v, lbuf, tw, j);
         cpx<R>* dst = stack + ((size_t)t * Np + (rt * kTileR + g * NL + line)) * Np;
 #pragma unroll

@@ -86,7 +86,7 @@ struct wsg_plan {
 namespace {
 
 struct Layout {
-    size_t stack, inter, rec, rec2, count, start, cursor, bsums, cls, occ, skipped, total;
+    size_t stack, inter, rec, rec2, part, count, start, cursor, bsums, cls, occ, skipped, total;
     int nbins, nscan;
 };
 
@@ -112,6 +112,7 @@ Layout layout_of(const wsg_plan* p, int prec, int64_t M) {
     L.inter = off;   off += al256(nl * N * Np * cs);
     L.rec = off;     off += al256(size_t(M) * rs);
     L.rec2 = off;    off += al256(size_t(M) * rs);
+    L.part = off;    off += al256(size_t(8) * size_t(M) * cs);   // degrid: per-tile parts
     L.total = off;
     return L;
 }
@@ -152,21 +153,23 @@ void scan(const uint32_t* count, uint32_t* start, uint32_t* bsums, int n, hipStr
 
 template <typename R, int W>
 void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
-                    const uint8_t* occ, const DevParams& P, const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
+                    const uint8_t* occ, const DevParams& P, const R* coef, cpx<R>* stack, cpx<R>* part,
+                    size_t part_stride, hipStream_t s) {
     if (grid)
         hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, occ, P, coef,
                            stack);
     else
         hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, P, coef,
-                           (const cpx<R>*)stack, vis);
+                           (const cpx<R>*)stack, part, part_stride);
 }
 
 template <typename R>
 void launch_tiles(bool grid, int W, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
-                  const uint8_t* occ, const DevParams& P, const R* coef, cpx<R>* stack, R* vis, hipStream_t s) {
+                  const uint8_t* occ, const DevParams& P, const R* coef, cpx<R>* stack, cpx<R>* part,
+                  size_t part_stride, hipStream_t s) {
     switch (W) {
 #define WSG_W(w) \
-    case w: launch_tiles_w<R, w>(grid, nblocks, rec, start, cls, occ, P, coef, stack, vis, s); break;
+    case w: launch_tiles_w<R, w>(grid, nblocks, rec, start, cls, occ, P, coef, stack, part, part_stride, s); break;
         WSG_W(1) WSG_W(2) WSG_W(3) WSG_W(4) WSG_W(5) WSG_W(6) WSG_W(7) WSG_W(8)
         WSG_W(9) WSG_W(10) WSG_W(11) WSG_W(12) WSG_W(13) WSG_W(14) WSG_W(15) WSG_W(16)
 #undef WSG_W
@@ -192,7 +195,8 @@ void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, cpx<R>* sta
     } else {
         {
             StageMark mark(s, 5);
-            hipLaunchKernelGGL((k_degrid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s, image, corr,
+            const unsigned grid_bq = unsigned((P.N + C::kNLt - 1) / C::kNLt);
+            hipLaunchKernelGGL((k_degrid_fft_b<R, LOGN>), dim3(grid_bq), dim3(C::kNLt * C::T), 0, s, image, corr,
                                tw, inter, P);
         }
         StageMark mark(s, 6);
@@ -281,14 +285,20 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
     if (grid) {
         {
             StageMark mark(s, 1);
-            launch_tiles<R>(true, P.W, L.nbins, rec, start, cls, occ, P, coef, stack, nullptr, s);
+            launch_tiles<R>(true, P.W, L.nbins, rec, start, cls, occ, P, coef, stack, nullptr, 0, s);
         }
         launch_fft<R>(true, plan->log2_np, P, occ, stack, inter, tw, corr, nullptr, static_cast<R*>(out), s);
     } else {
         launch_fft<R>(false, plan->log2_np, P, occ, stack, inter, tw, corr, static_cast<const R*>(in), nullptr, s);
+        fill<R>(static_cast<R*>(out), size_t(2 * M), R(0), s);     // skipped visibilities stay zero
         StageMark mark(s, 7);
-        fill<R>(static_cast<R*>(out), size_t(2 * M), R(0), s);
-        if (M > 0) launch_tiles<R>(false, P.W, L.nbins, rec, start, cls, occ, P, coef, stack, static_cast<R*>(out), s);
+        if (M > 0) {
+            auto* part = reinterpret_cast<cpx<R>*>(w + L.part);
+            launch_tiles<R>(false, P.W, L.nbins, rec, start, cls, occ, P, coef, stack, part, size_t(M), s);
+            hipLaunchKernelGGL(k_degrid_finish<R>, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s,
+                               (const Rec<R>*)rec, (const uint32_t*)(start + L.nbins), (const cpx<R>*)part,
+                               size_t(M), P.W, static_cast<cpx<R>*>(out));
+        }
     }
     WSG_HIP(hipGetLastError());
     return WSG_OK;

@@ -187,3 +187,39 @@ def test_repeated_calls_reuse_workspace():
     op, lm = make_plan(N, L, W, x0, wmax), least_misfit(W, x0)
     assert rel(b, wstack.grid(op, lm, uvw[:300], vis[:300])) <= 1e-10
     assert rel(a, wstack.grid(op, lm, uvw, vis)) <= 1e-10
+
+
+def _check_both(N, L, W, x0, wmax, uvw, vis, img):
+    op, lm = make_plan(N, L, W, x0, wmax), least_misfit(W, x0)
+    ref_g = wstack.grid(op, lm, uvw, vis)
+    ref_d = wstack.degrid(op, lm, uvw, img)
+    plan = plan_for(N, L, W, x0, wmax)
+    for prec, tol in ((64, 1e-10), (32, 1e-6)):
+        g = gpu_grid(plan, uvw, vis, prec)
+        d = gpu_degrid(plan, uvw, img, prec)
+        assert rel(g, ref_g) <= tol, (prec, "grid", rel(g, ref_g))
+        assert rel(d, ref_d) <= tol, (prec, "degrid", rel(d, ref_d))
+        assert maxrel(g, ref_g) <= 10 * tol and maxrel(d, ref_d) <= 10 * tol
+
+
+def test_earth_rotation_tracks():
+    """Time-major tracks (16 antennas, 120 baselines x 400 dumps = 48,000
+    visibilities, 2 binning chunks): consecutive records of a tile share their
+    support box for long runs and then move by one cell, the case the scatter's
+    and gather's residue-class registers are built for."""
+    N, L, W, x0 = 256, 0.3, 7, 0.25
+    uvw = inputs.array_uvw(16, 5000.0, -30.0, -30.0, 1.0, 400, 1.4e9, seed=5)
+    uvw = inputs.scale_to_image(uvw, N, L)
+    wmax = float(np.max(np.abs(uvw[:, 2]))) * 1.001
+    _check_both(N, L, W, x0, wmax, uvw, inputs.random_vis(uvw.shape[0], 6), inputs.random_image(N, 7))
+
+
+def test_binning_table_overflow():
+    """40,000 uniform visibilities over 2 x 64 x 64 bins: a binning chunk meets
+    more distinct bins than its LDS table holds, so many take the direct
+    counter path; counts and cursors must still agree."""
+    N, L, W, x0, wmax = 512, 0.3, 7, 0.25, 300.0
+    op = make_plan(N, L, W, x0, wmax)
+    assert op.Nprime == 1024 and 16 < op.n_layers <= 32
+    uvw = inputs.uniform_uvw(40000, 0.95 * N / (2 * L), wmax, 41)
+    _check_both(N, L, W, x0, wmax, uvw, inputs.random_vis(40000, 42), inputs.random_image(N, 43))
