@@ -81,7 +81,9 @@ def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict) 
     return {
         "grid_bin": M * (2 * 24 + b + rec) + sort,      # uvw read twice, vis, records written, sorted
         "grid_tiles": ws["tile_visits"] * rec + tiles,  # records in (once per tile reached), tiles out
-        "grid_fft_v": tiles + inter,                    # occupied tiles in, intermediate out
+        "grid_fft_v": tiles + inter,                    # occupied tiles in, intermediate lines out
+        "grid_transpose": 2 * inter,                    # intermediate in and out
+        "degrid_transpose": 2 * inter,
         "grid_fft_u": inter + 2 * N * N * r,            # intermediate, correction in, map out
         "degrid_bin": M * (2 * 24 + rec) + sort,
         "degrid_fft_p": 2 * N * N * r + inter,          # image, correction in, intermediate out
@@ -184,14 +186,17 @@ def cpu_baseline(w: dict, n_sample: int) -> dict:
     }
 
 
-def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int, ws: dict) -> dict:
+def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int, ws: dict, calls: int) -> dict:
+    """Per call of grid or degrid: stage time (HIP events on the launch stream,
+    summed over the stage's launches) and algorithmic bytes."""
     tab = {}
     for name, (ms, n) in stages.items():
         if n == 0:
             continue
-        per = ms / n
+        per = ms / calls
         nbytes = stage_bytes(name, M, N, Np, nl, f64, ws)
-        tab[name] = {"ms": per, "launches": n, "alg_bytes": nbytes, "alg_GBps": nbytes / (per * 1e-3) / 1e9}
+        tab[name] = {"ms": per, "launches_per_call": n / calls, "alg_bytes": nbytes,
+                     "alg_GBps": nbytes / (per * 1e-3) / 1e9}
     return tab
 
 
@@ -271,7 +276,7 @@ def main() -> int:
     ms32, stages32 = timed(step32, args.steps)
     log(f"fp32: {ms32:.3f} ms/step, {M / (ms32 * 1e-3):.4e} vis/s")
     skipped = plan.skipped(wsgrid.WSG_F32)
-    tab32 = stage_table(stages32, False, M, N, Np, nl, ws)
+    tab32 = stage_table(stages32, False, M, N, Np, nl, ws, args.steps)
 
     fp64, acc = None, None
     if args.fp64_steps > 0:
@@ -287,7 +292,7 @@ def main() -> int:
         ms64, stages64 = timed(step64, args.fp64_steps)
         log(f"fp64: {ms64:.3f} ms/step, {M / (ms64 * 1e-3):.4e} vis/s")
         fp64 = {"value": M / (ms64 * 1e-3), "ms_per_step": ms64,
-                "stages": stage_table(stages64, True, M, N, Np, nl, ws)}
+                "stages": stage_table(stages64, True, M, N, Np, nl, ws, args.fp64_steps)}
 
         def relrms(a, b):
             return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
@@ -299,7 +304,8 @@ def main() -> int:
     d = tab32[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic_for(dom, "f32"),
-                "alg_bytes_per_launch": d["alg_bytes"], "ms_per_launch": d["ms"]}
+                "alg_bytes_per_call": d["alg_bytes"], "ms_per_call": d["ms"],
+                "launches_per_call": d["launches_per_call"]}
     total_alg = sum(stage_bytes(s, M, N, Np, nl, False, ws) for s in tab32)
     result = {
         "metric": "visibilities/s grid+degrid at W=7,x0=0.25, FP32 vs FP64, at <=1e-6 DFT error",

@@ -125,13 +125,14 @@ int64_t grid_skipped(const wsg_plan* plan, const void* ws, void* stream);
  * records HIP events on its stream around each stage:
  *   0 grid binning (fold, count, scan, scatter)   4 degrid binning
  *   1 grid 3-D scatter tiles                     5 degrid FFT pass along p (+ w-screen)
- *   2 grid FFT pass along v (+ crop, transpose)  6 degrid FFT pass along q
+ *   2 grid FFT pass along v (+ crop)             6 degrid FFT pass along q
  *   3 grid FFT pass along u (+ w-screen, sum)    7 degrid 3-D gather tiles
+ *   8 grid intermediate transpose                9 degrid intermediate transpose
  * wsg_stage_times() waits for the recorded events, writes the summed
  * milliseconds and launch counts of the first n stages (either pointer may be
  * NULL), clears the record and returns WSG_NSTAGES (or < 0 on error).
  */
-#define WSG_NSTAGES 8
+#define WSG_NSTAGES 10
 void wsg_stage_timing(int enable);
 int wsg_stage_times(double* ms, int* launches, int n);
 

@@ -850,10 +850,10 @@ __global__ void k_degrid_finish(const Rec<R>* __restrict__ rec, const uint32_t* 
 
 // --------------------------------------------------------------- FFT passes --
 //
-// Stack layout [t][r][s] (s fastest).  Intermediate: grid [t][q][r] (r fastest),
-// degrid [t][r][q] (q fastest); q is the image row.  Each direction's transpose
-// is done on its write side, where narrow runs are merged in L2, so that the
-// reads are whole lines.  Image rows j <-> q and columns i <-> p.  The FFT output bin
+// Stack layout [t][r][s] (s fastest).  Every FFT pass reads and writes whole
+// lines: grid writes [t][r][q] and reads [t][q][r], degrid writes [t][q][r] and
+// reads [t][r][q], with k_transpose in between (q is the image row).  Image
+// rows j <-> q and columns i <-> p.  The FFT output bin
 // f of a line maps to image index (f + N/2) mod N' and is kept when below N
 // (Algorithm 5 step 3c); the degrid input places image index p at bin
 // (p - N/2) mod N' (zero padding, Algorithm 6 step 3b).
@@ -874,10 +874,11 @@ struct FftCfg {
 };
 
 // grid pass A: IFFT along s of stack rows [t][r][:], keep image rows q, write
-// the intermediate transposed [t][q][r].  One block per layer and row of tiles
-// (kTileR stack rows, taken NL at a time); the next NL rows are loaded while
-// the current ones are transformed.  Unmarked tiles are read as zero, and a
-// row of tiles with none marked is written as zeros without a transform.
+// the lines [t][r][q] (transposed afterwards by k_transpose).  One block per
+// layer and row of tiles (kTileR stack rows, taken NL at a time); the next NL
+// rows are loaded while the current ones are transformed.  Unmarked tiles are
+// read as zero, and a row of tiles with none marked is written as zeros
+// without a transform.
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_grid_fft_a(const cpx<R>* __restrict__ stack, const uint8_t* __restrict__ occ, cpx<R>* __restrict__ inter,
@@ -899,10 +900,9 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
         on[k] = orow[(size_t)((j + T * k) / kTileS) * nbr] != 0;
         any = any || on[k];
     }
-    cpx<R>* dst0 = inter + (size_t)t * N * Np + rt * kTileR;
+    cpx<R>* dst0 = inter + ((size_t)t * Np + rt * kTileR) * N;
     if (!__syncthreads_or(any)) {
-        for (int idx = threadIdx.x; idx < N * kTileR; idx += NL * T)
-            dst0[(size_t)(idx / kTileR) * Np + idx % kTileR] = cpx<R>{R(0), R(0)};
+        for (int idx = threadIdx.x; idx < N * kTileR; idx += NL * T) dst0[idx] = cpx<R>{R(0), R(0)};
         return;
     }
     auto load = [&](int g, cpx<R> (&v)[16]) {
@@ -919,15 +919,12 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
         for (int k = 0; k < 16; ++k) v[k] = nx[k];
         if (g + 1 < NG) load(g + 1, nx);
         fft_line<R, LOGN, +1>(v, lbuf, tw, j);
-        __syncthreads();
+        // bin f = j + T k holds image row q = (f + N/2) mod N', kept when below N
+        cpx<R>* dst = dst0 + (size_t)(g * NL + line) * N;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) lbuf[lpad(j + T * k)] = v[k];
-        __syncthreads();
-        cpx<R>* dst = dst0 + g * NL;
-        for (int idx = threadIdx.x; idx < N * NL; idx += NL * T) {
-            const int q = idx / NL, l = idx % NL;
-            const int f = (q - half) & (Np - 1);
-            dst[(size_t)q * Np + l] = buf[l * LP + lpad(f)];
+        for (int k = 0; k < 16; ++k) {
+            const int q = (j + T * k + half) & (Np - 1);
+            if (q < N) dst[q] = v[k];
         }
     }
 }
@@ -986,21 +983,17 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 }
 
 // degrid pass B': for each image row q and layer t: f h_x h_y h_z exp(-i 2 pi t z)
-// zero-padded along p, FFT along p -> intermediate [t][r][q] (Algorithm 6 steps
-// 2-3).  A block takes NL consecutive rows; the transformed lines go through LDS
-// so that each frequency r is written as a run of NL consecutive q (the narrow
-// runs are on the write side, where the L2 merges them).
+// zero-padded along p, FFT along p -> intermediate [t][q][r] (Algorithm 6 steps 2-3).
 template <typename R, int LOGN>
-__global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
+__global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
     k_degrid_fft_b(const R* __restrict__ image, const R* __restrict__ corr, const cpx<R>* __restrict__ tw,
                    cpx<R>* __restrict__ inter, DevParams P) {
     using C = FftCfg<R, LOGN>;
-    constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size;
+    constexpr int Np = C::N, T = C::T, NL = C::kNLr, LP = LinePad<Np>::size;
     __shared__ cpx<R> buf[NL * LP];
     const int N = P.N, half = N / 2;
     const int line = threadIdx.x / T, j = threadIdx.x % T;
-    const int q0 = xcd_remap(blockIdx.x, gridDim.x) * NL;
-    const int q = q0 + line;
+    const int q = xcd_remap(blockIdx.x, gridDim.x) * NL + line;
     const bool row_ok = q < N;
     const int qq = row_ok ? q : 0;
     cpx<R>* lbuf = buf + line * LP;
@@ -1018,7 +1011,6 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
         const double nm1 = -r2 / (1.0 + sqrt(1.0 - r2));
         z[k] = nm1 / P.nscale + P.z0;
     }
-    const int nq = min(NL, N - q0);
     for (int t = 0; t < P.n_layers; ++t) {
         const double tl = double(t + P.t_lo);
         cpx<R> v[16];
@@ -1029,14 +1021,10 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
             v[k] = cpx<R>{g[k] * c, g[k] * s};
         }
         fft_line<R, LOGN, -1>(v, lbuf, tw, j);
-        __syncthreads();
+        if (row_ok) {
+            cpx<R>* dst = inter + ((size_t)t * N + q) * Np;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) lbuf[lpad(j + T * k)] = v[k];
-        __syncthreads();
-        cpx<R>* dst = inter + (size_t)t * Np * N + q0;
-        for (int idx = threadIdx.x; idx < Np * NL; idx += NL * T) {
-            const int r = idx / NL, l = idx % NL;
-            if (l < nq) dst[(size_t)r * N + l] = buf[l * LP + lpad(r)];
+            for (int k = 0; k < 16; ++k) dst[j + T * k] = v[k];
         }
     }
 }
@@ -1091,6 +1079,29 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
 #pragma unroll
         for (int k = 0; k < 16; ++k)
             if (on[k]) dst[j + T * k] = v[k];
+    }
+}
+
+// out[t][b][a] = in[t][a][b] for a < A, b < B, through a 64 x 64 LDS tile:
+// reads and writes are whole 64-element rows (512 B FP32) away from the edges.
+template <typename R>
+__global__ void __launch_bounds__(256) k_transpose(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int A,
+                                                   int B) {
+    __shared__ cpx<R> tile[64][65];
+    const int ta_n = (A + 63) / 64, tb_n = (B + 63) / 64;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = lb / (ta_n * tb_n), rem = lb % (ta_n * tb_n);
+    const int a0 = (rem / tb_n) * 64, b0 = (rem % tb_n) * 64;
+    const cpx<R>* src = in + (size_t)t * A * B;
+    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+        const int a = a0 + i / 64, b = b0 + i % 64;
+        if (a < A && b < B) tile[i / 64][i % 64] = src[(size_t)a * B + b];
+    }
+    __syncthreads();
+    cpx<R>* dst = out + (size_t)t * A * B;
+    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+        const int b = b0 + i / 64, a = a0 + i % 64;
+        if (a < A && b < B) dst[(size_t)b * A + a] = tile[i % 64][i / 64];
     }
 }
 

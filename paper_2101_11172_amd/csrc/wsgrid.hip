@@ -53,6 +53,7 @@ struct StageMark {
     int stage;
     hipEvent_t a = nullptr;
     StageMark(hipStream_t s_, int st) : s(s_), stage(st) {
+        static_assert(WSG_NSTAGES == 10, "stage ids are listed in wsgrid.h");
         if (g_timing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
     }
     ~StageMark() {
@@ -86,7 +87,7 @@ struct wsg_plan {
 namespace {
 
 struct Layout {
-    size_t stack, inter, rec, rec2, part, count, start, cursor, bsums, cls, occ, skipped, total;
+    size_t stack, inter, inter2, rec, rec2, part, count, start, cursor, bsums, cls, occ, skipped, total;
     int nbins, nscan;
 };
 
@@ -110,6 +111,7 @@ Layout layout_of(const wsg_plan* p, int prec, int64_t M) {
     L.occ = off;     off += al256(size_t(L.nbins));
     L.stack = off;   off += al256(nl * Np * Np * cs);
     L.inter = off;   off += al256(nl * N * Np * cs);
+    L.inter2 = off;  off += al256(nl * N * Np * cs);   // the transposed intermediate
     L.rec = off;     off += al256(size_t(M) * rs);
     L.rec2 = off;    off += al256(size_t(M) * rs);
     L.part = off;    off += al256(size_t(8) * size_t(M) * cs);   // degrid: per-tile parts
@@ -177,8 +179,14 @@ void launch_tiles(bool grid, int W, int nblocks, const Rec<R>* rec, const uint32
     }
 }
 
+template <typename R>
+void transpose(const DevParams& P, const cpx<R>* in, cpx<R>* out, int A, int B, hipStream_t s) {
+    const unsigned blocks = unsigned(P.n_layers) * unsigned((A + 63) / 64) * unsigned((B + 63) / 64);
+    hipLaunchKernelGGL(k_transpose<R>, dim3(blocks), dim3(256), 0, s, in, out, A, B);
+}
+
 template <typename R, int LOGN>
-void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, cpx<R>* stack, cpx<R>* inter,
+void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, cpx<R>* stack, cpx<R>* inter, cpx<R>* inter2,
                   const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
     using C = FftCfg<R, LOGN>;
     const unsigned grid_a = unsigned(P.n_layers) * unsigned(C::N / kTileR);
@@ -189,28 +197,35 @@ void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, cpx<R>* sta
             hipLaunchKernelGGL((k_grid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
                                (const cpx<R>*)stack, occ, inter, tw, P.N, P.n_layers, P.nbr);
         }
+        {
+            StageMark mark(s, 8);
+            transpose<R>(P, inter, inter2, P.Np, P.N, s);          // [t][r][q] -> [t][q][r]
+        }
         StageMark mark(s, 3);
         hipLaunchKernelGGL((k_grid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
-                           (const cpx<R>*)inter, tw, corr, dirty, P);
+                           (const cpx<R>*)inter2, tw, corr, dirty, P);
     } else {
         {
             StageMark mark(s, 5);
-            const unsigned grid_bq = unsigned((P.N + C::kNLt - 1) / C::kNLt);
-            hipLaunchKernelGGL((k_degrid_fft_b<R, LOGN>), dim3(grid_bq), dim3(C::kNLt * C::T), 0, s, image, corr,
+            hipLaunchKernelGGL((k_degrid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s, image, corr,
                                tw, inter, P);
+        }
+        {
+            StageMark mark(s, 9);
+            transpose<R>(P, inter, inter2, P.N, P.Np, s);          // [t][q][r] -> [t][r][q]
         }
         StageMark mark(s, 6);
         hipLaunchKernelGGL((k_degrid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
-                           (const cpx<R>*)inter, occ, tw, stack, P.N, P.n_layers, P.nbr);
+                           (const cpx<R>*)inter2, occ, tw, stack, P.N, P.n_layers, P.nbr);
     }
 }
 
 template <typename R>
 void launch_fft(bool grid, int log2n, const DevParams& P, const uint8_t* occ, cpx<R>* stack, cpx<R>* inter,
-                const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
+                cpx<R>* inter2, const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
     switch (log2n) {
 #define WSG_N(n) \
-    case n: launch_fft_n<R, n>(grid, P, occ, stack, inter, tw, corr, image, dirty, s); break;
+    case n: launch_fft_n<R, n>(grid, P, occ, stack, inter, inter2, tw, corr, image, dirty, s); break;
         WSG_N(6) WSG_N(7) WSG_N(8) WSG_N(9) WSG_N(10) WSG_N(11) WSG_N(12) WSG_N(13)
 #undef WSG_N
         default: break;
@@ -244,6 +259,7 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
     char* w = static_cast<char*>(ws);
     auto* stack = reinterpret_cast<cpx<R>*>(w + L.stack);
     auto* inter = reinterpret_cast<cpx<R>*>(w + L.inter);
+    auto* inter2 = reinterpret_cast<cpx<R>*>(w + L.inter2);
     auto* rec_bin = reinterpret_cast<Rec<R>*>(w + L.rec2);   // binned, unordered within a bin
     auto* rec = reinterpret_cast<Rec<R>*>(w + L.rec);        // binned and sorted within each bin
     auto* count = reinterpret_cast<uint32_t*>(w + L.count);
@@ -287,9 +303,10 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
             StageMark mark(s, 1);
             launch_tiles<R>(true, P.W, L.nbins, rec, start, cls, occ, P, coef, stack, nullptr, 0, s);
         }
-        launch_fft<R>(true, plan->log2_np, P, occ, stack, inter, tw, corr, nullptr, static_cast<R*>(out), s);
+        launch_fft<R>(true, plan->log2_np, P, occ, stack, inter, inter2, tw, corr, nullptr, static_cast<R*>(out), s);
     } else {
-        launch_fft<R>(false, plan->log2_np, P, occ, stack, inter, tw, corr, static_cast<const R*>(in), nullptr, s);
+        launch_fft<R>(false, plan->log2_np, P, occ, stack, inter, inter2, tw, corr, static_cast<const R*>(in), nullptr,
+                      s);
         fill<R>(static_cast<R*>(out), size_t(2 * M), R(0), s);     // skipped visibilities stay zero
         StageMark mark(s, 7);
         if (M > 0) {
@@ -380,8 +397,10 @@ int wsg_stage_times(double* ms, int* launches, int n) {
             if (err == hipSuccess) err = hipEventElapsedTime(&t, e.a, e.b);
             if (err != hipSuccess) rc = fail(WSG_EHIP, std::string("stage timing: ") + hipGetErrorString(err));
         }
-        acc[e.stage] += t;
-        cnt[e.stage] += 1;
+        if (e.stage >= 0 && e.stage < WSG_NSTAGES) {
+            acc[e.stage] += t;
+            cnt[e.stage] += 1;
+        }
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
     }
