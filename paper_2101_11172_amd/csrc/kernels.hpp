@@ -519,7 +519,7 @@ __device__ __forceinline__ int word_bits(double v) { return __double2loint(v); }
 // move by one cell.
 template <typename R, int W>
 struct ScatterCfg {
-    static constexpr int kWaveBatch = sizeof(R) == 8 ? 32 : 64;    // records per wave round
+    static constexpr int kWaveBatch = 32;      // records per wave round (small stage: 3 blocks per CU)
     static constexpr int kSlots = 4 * kWaveBatch;
     static constexpr int kPairs = W * W;
     static constexpr int kPI = (kPairs + 63) / 64;                // (x, y) residue pairs per lane
