@@ -243,3 +243,32 @@ class Plan:
     def skipped(self, prec: int) -> int:
         ws = self._ws[prec]
         return grid_skipped(self._p, ws.data_ptr(), torch.cuda.current_stream(self.device).cuda_stream)
+
+
+class DegridFn(torch.autograd.Function):
+    """Model visibilities of a real image as a differentiable torch operation.
+
+    forward: degrid_visibilities (Algorithm 6).  backward: grid_visibilities
+    (Algorithm 5) applied to the incoming gradient.  For a real image f and
+    vis = A f, torch's gradient for a complex output is g = dL/dRe(vis) +
+    i dL/dIm(vis), so dL/df = Re(A^H g); the gridding operator returns exactly
+    Re(A^H g), the two being adjoint (Sec. 3.1-3.2, eq. gridded-dirty-map).
+    The precision follows the image (float32 -> complex64 visibilities and a
+    float32 gradient).  uvw carries no gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, image: torch.Tensor, plan: "Plan", uvw: torch.Tensor) -> torch.Tensor:
+        ctx.plan = plan
+        ctx.save_for_backward(uvw)
+        return plan.degrid(uvw, image.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_vis: torch.Tensor):
+        (uvw,) = ctx.saved_tensors
+        return ctx.plan.grid(uvw, grad_vis.contiguous()), None, None
+
+
+def degrid_fn(plan: Plan, uvw: torch.Tensor, image: torch.Tensor) -> torch.Tensor:
+    """Differentiable degrid: DegridFn.apply(image, plan, uvw)."""
+    return DegridFn.apply(image, plan, uvw)
