@@ -706,17 +706,20 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     }
 }
 
-// Gather: lanes over records.  The tile sits in LDS as complex cells with a
-// zero guard of 17 (W - 1) cells before and after, so that for any support
-// start (dr, ds) in [-(W-1), 15] the cell address base + 16 x + y of every
-// support offset is inside the array.  Each lane evaluates its own record's
-// weights, sets those of out-of-tile indices to zero (the cells read there are
-// finite neighbours or guard zeros), clamps the layer of each residue and sums
-// the W^3 products; no cross-lane reduction is needed.
+// Gather: lanes over records.  The tile sits in LDS as complex cells, rows
+// kLR = 17 cells and layers kLT = 16 kLR + 1 cells apart (the padding cells are
+// zero), with a zero guard of (kLR + 1)(W - 1) cells before and after, so that
+// for any support start (dr, ds) in [-(W-1), 15] the cell address
+// base + kLR x + y of every support offset is inside the array.  Each lane
+// evaluates its own record's weights, sets those of out-of-tile indices to zero
+// (the cells read there are finite neighbours or zeros), clamps the layer of
+// each residue and sums the W^3 products; no cross-lane reduction is needed.
 template <typename R, int W>
 struct GatherCfg {
-    static constexpr int kGuard = 17 * (W - 1);
-    static constexpr int kCells = kTileT * kTileR * kTileS;
+    static constexpr int kLR = kTileS + 1;              // row stride (cells): skews rows and
+    static constexpr int kLT = kTileR * kLR + 1;        // layers over the LDS banks
+    static constexpr int kGuard = (kLR + 1) * (W - 1);
+    static constexpr int kCells = kTileT * kLT;
     static constexpr int kLen = kCells + 2 * kGuard;
 };
 
@@ -761,9 +764,10 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     for (int i = tid; i < G::kLen; i += 256) {
         const int c = i - G::kGuard;
         cpx<R> q{R(0), R(0)};
-        if (c >= 0 && c < nt_valid * kTileR * kTileS) {
-            const int ss = c % kTileS, rr = (c / kTileS) % kTileR, tt = c / (kTileR * kTileS);
-            q = stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)];
+        if (c >= 0 && c < G::kCells) {
+            const int tt = c / G::kLT, rem = c % G::kLT, rr = rem / G::kLR, ss = rem % G::kLR;
+            if (tt < nt_valid && rr < kTileR && ss < kTileS)
+                q = stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)];
         }
         g[i] = q;
     }
@@ -792,19 +796,19 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
             wv_[a] = unsigned(ds + a) < unsigned(kTileS) ? wv_[a] : R(0);
             wt[a] = unsigned(dt + a) < unsigned(nt_valid) ? wt[a] : R(0);
         }
-        const cpx<R>* row = g + (G::kGuard + dr * kTileS + ds);
+        const cpx<R>* row = g + (G::kGuard + dr * G::kLR + ds);
         R sx = R(0), sy = R(0);
 #pragma unroll
         for (int a = 0; a < W; ++a) {
             const int tt = min(max(dt + a, 0), kTileT - 1);
-            const cpx<R>* pa = row + tt * (kTileR * kTileS);
+            const cpx<R>* pa = row + tt * G::kLT;
             R ax = R(0), ay = R(0);
 #pragma unroll
             for (int x = 0; x < W; ++x) {
                 R bx = R(0), by = R(0);
 #pragma unroll
                 for (int y = 0; y < W; ++y) {
-                    const cpx<R> q = pa[x * kTileS + y];
+                    const cpx<R> q = pa[x * G::kLR + y];
                     bx += q.x * wv_[y];
                     by += q.y * wv_[y];
                 }
