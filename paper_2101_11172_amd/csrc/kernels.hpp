@@ -507,8 +507,8 @@ __device__ __forceinline__ int word_bits(double v) { return __double2loint(v); }
 // owns, among the W x W x W support cells of a record, the W cells whose u and
 // v indices are congruent to x and y modulo W, one per layer residue a: for
 // support start (dr, ds, dt) the u-cell dr + ((x - dr) mod W), the v-cell
-// ds + ((y - ds) mod W) and the layer dt + ((a - dt) mod W).  Each lane stages
-// one record per round into its wave's slots: the u weights times the value
+// ds + ((y - ds) mod W) and the layer dt + ((a - dt) mod W).  Each round a wave
+// stages 32 records into its slots (two lanes per record): the u weights times the value
 // and the v weights rotated by the support start (so lane x reads position x
 // whatever the record), and the layer weights rotated by dt with the packed
 // support start, read by the whole wave as broadcasts.  Sums stay in registers
@@ -637,35 +637,52 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
         };
 
         const int slot0 = wv * WB;
+        // staging: lanes rl and rl + 32 take record rl, the first the kernel
+        // segments [0, A0), the second [A0, W), so the Horner work is spread
+        // over the whole wave
+        static_assert(2 * WB == 64, "two lanes per staged record");
+        constexpr int A0 = (W + 1) / 2;
+        const int rl = lane & (WB - 1), half = lane / WB;
         Rec<R> nxt;
-        if (lane < WB && q0 + uint32_t(lane) < q1) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(lane))];
+        if (q0 + uint32_t(rl) < q1) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(rl))];
         for (uint32_t base = q0; base < q1; base += WB) {
             const int n = int(min(uint32_t(WB), q1 - base));
-            if (lane < n) {
+            if (rl < n) {
                 // stage: rotated weights, value folded into the u weights
                 const int dr = wrap_offset(int(nxt.ruv & 0xffffu), r0, P.Np);
                 const int ds = wrap_offset(int(nxt.ruv >> 16), s0, P.Np);
                 const int dt = int(nxt.rt) - t0;
-                R wu[W], wv_[W], wt[W];
-                record_weights<R, W>(nxt, coef, wu, wv_, wt);
                 const int pr = mod_w<W>(dr), ps = mod_w<W>(ds), pt = mod_w<W>(dt);
-                const int slot = slot0 + lane;
+                const int slot = slot0 + rl;
 #pragma unroll
-                for (int a = 0; a < W; ++a) {
-                    int ku = pr + a, kv = ps + a, kt = pt + a;
-                    ku -= ku >= W ? W : 0;
-                    kv -= kv >= W ? W : 0;
-                    kt -= kt >= W ? W : 0;
-                    st.wuv[slot][ku] = nxt.v[0] * wu[a];
-                    st.wuv[slot][W + ku] = nxt.v[1] * wu[a];
-                    st.wuv[slot][2 * W + kv] = wv_[a];
-                    st.words[slot][kt] = wt[a];
+                for (int i = 0; i < A0; ++i) {
+                    const int a = i + half * A0;
+                    const R* c = coef + min(a, W - 1) * (D + 1);
+                    R hu = c[D], hv = c[D], ht = c[D];
+#pragma unroll
+                    for (int k = D - 1; k >= 0; --k) {
+                        const R ck = c[k];
+                        hu = hu * nxt.nu[0] + ck;
+                        hv = hv * nxt.nu[1] + ck;
+                        ht = ht * nxt.nu[2] + ck;
+                    }
+                    if (a < W) {
+                        int ku = pr + a, kv = ps + a, kt = pt + a;
+                        ku -= ku >= W ? W : 0;
+                        kv -= kv >= W ? W : 0;
+                        kt -= kt >= W ? W : 0;
+                        st.wuv[slot][ku] = nxt.v[0] * hu;
+                        st.wuv[slot][W + ku] = nxt.v[1] * hu;
+                        st.wuv[slot][2 * W + kv] = hv;
+                        st.words[slot][kt] = ht;
+                    }
                 }
-                st.words[slot][W] = bits_to_word((dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16), R(0));
+                if (half == 0)
+                    st.words[slot][W] = bits_to_word((dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16), R(0));
             }
             wave_sync();
-            const uint32_t vn = base + WB + uint32_t(lane);
-            if (lane < WB && vn < q1) nxt = rec[seg_index(sg, nseg, vn)];
+            const uint32_t vn = base + WB + uint32_t(rl);
+            if (vn < q1) nxt = rec[seg_index(sg, nseg, vn)];
 
             for (int j = 0; j < n; ++j) {
                 const int slot = slot0 + j;
