@@ -87,8 +87,10 @@ int grid_plan_info(const wsg_plan* plan, int* Nprime, int* t_lo, int* n_layers,
 /*
  * Device workspace (bytes) that one grid_visibilities or degrid_visibilities
  * call with M visibilities at precision `prec` needs: the w-layer stack
- * (n_layers N'^2 complex), the FFT intermediate (n_layers N N' complex), the
- * binned visibility records (M records) and bin tables.  0 on a bad argument.
+ * (n_layers N'^2 complex; only tiles some visibility reaches are touched), the
+ * FFT intermediate before and after its transpose (2 n_layers N N' complex),
+ * the binned visibility records (2 M records), the degrid per-tile parts
+ * (8 M complex) and the bin tables.  0 on a bad argument.
  */
 size_t grid_workspace_bytes(const wsg_plan* plan, int prec, int64_t M);
 

@@ -1,13 +1,18 @@
 // C-ABI of the wsgrid library: plans, workspace layout and the launch sequences
 // of Algorithm 5 (grid) and Algorithm 6 (degrid) on one gfx950 device.
 //
-// grid_visibilities:   bin (count, scan, scatter) -> k_grid_tiles (3-D scatter,
-//                      stack [t][r][s]) -> k_grid_fft_a (IFFT along s, crop,
-//                      transpose) -> k_grid_fft_b (IFFT along r, crop, w-screen,
-//                      sum over layers, correction) -> dirty [N][N]
-// degrid_visibilities: bin -> k_degrid_fft_b (correction, w-screen, pad, FFT
-//                      along p) -> k_degrid_fft_a (pad, FFT along q) ->
-//                      k_degrid_tiles (3-D gather, phase, fold) -> vis [M]
+// bin = k_bin_count, scan, k_bin_scatter, k_bin_local_sort (by touch class and
+//       support start), k_tile_occupancy
+// grid_visibilities:   bin -> k_grid_tiles (3-D scatter into the occupied tiles
+//                      of the stack [t][r][s]) -> k_grid_fft_a (IFFT along s,
+//                      crop, lines [t][r][q]) -> k_transpose ([t][q][r]) ->
+//                      k_grid_fft_b (IFFT along r, crop, w-screen, sum over
+//                      layers, correction) -> dirty [N][N]
+// degrid_visibilities: bin; k_degrid_fft_b (correction, w-screen, pad, FFT
+//                      along p, lines [t][q][r]) -> k_transpose ([t][r][q]) ->
+//                      k_degrid_fft_a (pad, FFT along q, occupied tiles) ->
+//                      k_degrid_tiles (3-D gather, one part per tile reached) ->
+//                      k_degrid_finish (sum of parts, phase, fold) -> vis [M]
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
