@@ -81,9 +81,9 @@ def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict) 
     return {
         "grid_bin": M * (2 * 24 + b + rec) + sort,      # uvw read twice, vis, records written, sorted
         "grid_tiles": ws["tile_visits"] * rec + tiles,  # records in (once per tile reached), tiles out
-        "grid_fft_v": tiles + inter,                    # occupied tiles in, intermediate lines out
-        "grid_transpose": 2 * inter,                    # intermediate in and out
-        "degrid_transpose": 2 * inter,
+        "grid_fft_v": tiles + inter_rows,               # occupied tiles in, lines of occupied rows out
+        "grid_transpose": inter_rows + inter,           # those lines in (the others are zero), all out
+        "degrid_transpose": inter_rows + inter_rows,    # lines the transform along q needs, in and out
         "grid_fft_u": inter + 2 * N * N * r,            # intermediate, correction in, map out
         "degrid_bin": M * (2 * 24 + rec) + sort,
         "degrid_fft_p": 2 * N * N * r + inter,          # image, correction in, intermediate out

@@ -355,7 +355,10 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
 // visibilities can reach it (its own and the seven one tile back) is non-empty.
 // Only marked tiles of the stack are written (grid) or filled (degrid); the FFT
 // passes treat unmarked tiles as zero (grid) or skip them (degrid).
-__global__ void k_tile_occupancy(const uint32_t* __restrict__ start, DevParams P, uint8_t* __restrict__ occ) {
+// A row of tiles (t tile, u tile) is marked in `rows` when one of its tiles is
+// occupied (`rows` zero on entry; racing stores all write 1).
+__global__ void k_tile_occupancy(const uint32_t* __restrict__ start, DevParams P, uint8_t* __restrict__ occ,
+                                 uint8_t* __restrict__ rows) {
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
     const int nt = P.nbt * P.nbs * P.nbr;
     if (tile >= nt) return;
@@ -370,6 +373,7 @@ __global__ void k_tile_occupancy(const uint32_t* __restrict__ start, DevParams P
             }
     }
     occ[tile] = any ? 1 : 0;
+    if (any) rows[bt * P.nbr + br] = 1;
 }
 
 // ------------------------------------------------ 3-D scatter / gather tiles --
@@ -898,8 +902,8 @@ struct FftCfg {
 // the lines [t][r][q] (transposed afterwards by k_transpose).  One block per
 // layer and row of tiles (kTileR stack rows, taken NL at a time); the next NL
 // rows are loaded while the current ones are transformed.  Unmarked tiles are
-// read as zero, and a row of tiles with none marked is written as zeros
-// without a transform.
+// read as zero; a row of tiles with none marked is neither transformed nor
+// written (its lines are zero).
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_grid_fft_a(const cpx<R>* __restrict__ stack, const uint8_t* __restrict__ occ, cpx<R>* __restrict__ inter,
@@ -922,10 +926,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
         any = any || on[k];
     }
     cpx<R>* dst0 = inter + ((size_t)t * Np + rt * kTileR) * N;
-    if (!__syncthreads_or(any)) {
-        for (int idx = threadIdx.x; idx < N * kTileR; idx += NL * T) dst0[idx] = cpx<R>{R(0), R(0)};
-        return;
-    }
+    if (!__syncthreads_or(any)) return;     // zero lines: the transpose reads them as zeros
     auto load = [&](int g, cpx<R> (&v)[16]) {
         const cpx<R>* src = stack + ((size_t)t * Np + (rt * kTileR + g * NL + line)) * Np;
 #pragma unroll
@@ -1105,24 +1106,37 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
 
 // out[t][b][a] = in[t][a][b] for a < A, b < B, through a 64 x 64 LDS tile:
 // reads and writes are whole 64-element rows (512 B FP32) away from the edges.
-template <typename R>
-__global__ void __launch_bounds__(256) k_transpose(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int A,
-                                                   int B) {
+// The stack frequency r (16 per row of tiles) is the row index a of the input
+// when R_IN, else the row index b of the output.  Lines of r whose row of
+// tiles (t / 16, r / 16) is not marked in `rows` are zero on input (R_IN: not
+// read) or not needed on output (not written; a tile with none needed is
+// skipped whole).
+template <typename R, int THREADS, bool R_IN>
+__global__ void __launch_bounds__(THREADS) k_transpose(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
+                                                       int A, int B, const uint8_t* __restrict__ rows, int nbr) {
     __shared__ cpx<R> tile[64][65];
+    __shared__ uint8_t live[4];
     const int ta_n = (A + 63) / 64, tb_n = (B + 63) / 64;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int t = lb / (ta_n * tb_n), rem = lb % (ta_n * tb_n);
     const int a0 = (rem / tb_n) * 64, b0 = (rem % tb_n) * 64;
+    const int r0 = R_IN ? a0 : b0;
+    if (threadIdx.x < 4) live[threadIdx.x] = rows[(t / kTileT) * nbr + min(r0 / kTileR + int(threadIdx.x), nbr - 1)];
+    __syncthreads();
+    if (!R_IN && !(live[0] | live[1] | live[2] | live[3])) return;
     const cpx<R>* src = in + (size_t)t * A * B;
-    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    for (int i = threadIdx.x; i < 64 * 64; i += THREADS) {
         const int a = a0 + i / 64, b = b0 + i % 64;
-        if (a < A && b < B) tile[i / 64][i % 64] = src[(size_t)a * B + b];
+        if (a < A && b < B) {
+            const bool on = !R_IN || live[(i / 64) / kTileR];
+            tile[i / 64][i % 64] = on ? src[(size_t)a * B + b] : cpx<R>{R(0), R(0)};
+        }
     }
     __syncthreads();
     cpx<R>* dst = out + (size_t)t * A * B;
-    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    for (int i = threadIdx.x; i < 64 * 64; i += THREADS) {
         const int b = b0 + i / 64, a = a0 + i % 64;
-        if (a < A && b < B) dst[(size_t)b * A + a] = tile[i % 64][i / 64];
+        if (a < A && b < B && (R_IN || live[(i / 64) / kTileR])) dst[(size_t)b * A + a] = tile[i % 64][i / 64];
     }
 }
 
