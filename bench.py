@@ -226,7 +226,7 @@ def main() -> int:
     ap.add_argument("--dumps", type=int, default=4960, help="time samples (M = 2016 x dumps)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="0 skips the FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=30000)
+    ap.add_argument("--cpu-sample", type=int, default=60000)
     ap.add_argument("--copy-gb", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GB (counter calibration)")
     args = ap.parse_args()
