@@ -55,12 +55,20 @@ def workload_stats(uvw, N: int, L: float, W: int, x0: float, wmax: float, Np: in
     nb, nbt = Np // T, (nl + T - 1) // T
     cnt = np.bincount((ft // T * nb + fv // T) * nb + fu // T, minlength=nbt * nb * nb).reshape(nbt, nb, nb)
     B = 17 - W
-    visits = int(np.sum((1 + (ft % T >= B)) * (1 + (fu % T >= B)) * (1 + (fv % T >= B))))
-    reach = cnt > 0
-    reach = reach | np.roll(reach, 1, axis=2)          # one tile back along u (periodic)
-    reach = reach | np.roll(reach, 1, axis=1)          # and along v
-    occ = reach.copy()
-    occ[1:] |= reach[:-1]                               # and along t (not periodic)
+    ct, cv, cu = ft % T >= B, fv % T >= B, fu % T >= B
+    visits = int(np.sum((1 + ct) * (1 + cu) * (1 + cv)))
+    occ = np.zeros((nbt, nb, nb), dtype=bool)          # tiles some visibility reaches
+    for it in (0, 1):
+        for iv in (0, 1):
+            for iu in (0, 1):
+                m = np.ones(ft.size, dtype=bool)
+                if it:
+                    m &= ct
+                if iv:
+                    m &= cv
+                if iu:
+                    m &= cu
+                occ[ft[m] // T + it, (fv[m] // T + iv) % nb, (fu[m] // T + iu) % nb] = True
     cells_per_t = np.array([min(T, nl - T * i) for i in range(nbt)]) * T * T
     occ_cells = int(np.sum(occ.sum(axis=(1, 2)) * cells_per_t))
     rows = occ.any(axis=1)                              # [t tile][u tile]: any tile along v

@@ -351,26 +351,36 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
     }
 }
 
-// Tile occupancy: a tile is marked when any of the eight bins whose
-// visibilities can reach it (its own and the seven one tile back) is non-empty.
-// Only marked tiles of the stack are written (grid) or filled (degrid); the FFT
-// passes treat unmarked tiles as zero (grid) or skip them (degrid).
-// A row of tiles (t tile, u tile) is marked in `rows` when one of its tiles is
-// occupied (`rows` zero on entry; racing stores all write 1).
-__global__ void k_tile_occupancy(const uint32_t* __restrict__ start, DevParams P, uint8_t* __restrict__ occ,
-                                 uint8_t* __restrict__ rows) {
+// Tile occupancy: a tile is marked when some visibility reaches it: its own bin
+// is non-empty, or the bin one tile back along the axes of a set m holds
+// visibilities whose touch class contains m (from the class starts of the
+// per-bin sort).  Only marked tiles of the stack are written (grid) or filled
+// (degrid); the FFT passes treat unmarked tiles as zero (grid) or skip them
+// (degrid).  A row of tiles (t tile, u tile) is marked in `rows` when one of
+// its tiles is (`rows` zero on entry; racing stores all write 1).
+__global__ void k_tile_occupancy(const uint32_t* __restrict__ start, const uint32_t* __restrict__ cls, DevParams P,
+                                 uint8_t* __restrict__ occ, uint8_t* __restrict__ rows) {
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
     const int nt = P.nbt * P.nbs * P.nbr;
     if (tile >= nt) return;
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
-    uint32_t any = 0;
-    for (int it = 0; it < 2; ++it) {
+    bool any = false;
+    for (int nb = 0; nb < 8 && !any; ++nb) {
+        const int it = (nb >> 2) & 1, is = (nb >> 1) & 1, ir = nb & 1;
         if (bt - it < 0) continue;
-        for (int is = 0; is < 2; ++is)
-            for (int ir = 0; ir < 2; ++ir) {
-                const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
-                any |= start[bin + 1] - start[bin];
+        const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
+        const uint32_t b0 = start[bin], b1 = start[bin + 1];
+        if (b1 == b0) continue;
+        const int m = it | (ir << 1) | (is << 2);
+        for (int q = 0; q < 8; ++q) {
+            const int c = q ^ (q >> 1);
+            if ((c & m) != m) continue;
+            const uint32_t lo = cls[8 * size_t(bin) + q], hi = q < 7 ? cls[8 * size_t(bin) + q + 1] : b1;
+            if (hi > lo) {
+                any = true;
+                break;
             }
+        }
     }
     occ[tile] = any ? 1 : 0;
     if (any) rows[bt * P.nbr + br] = 1;

@@ -313,8 +313,8 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
                                (const uint32_t*)start, cls, P);
         }
         fill<uint8_t>(rows, size_t(P.nbt) * P.nbr, uint8_t(0), s);
-        hipLaunchKernelGGL(k_tile_occupancy, dim3((L.nbins + 255) / 256), dim3(256), 0, s, (const uint32_t*)start, P,
-                           occ, rows);
+        hipLaunchKernelGGL(k_tile_occupancy, dim3((L.nbins + 255) / 256), dim3(256), 0, s, (const uint32_t*)start,
+                           (const uint32_t*)cls, P, occ, rows);
     }
     if (grid) {
         {
