@@ -48,7 +48,7 @@ enum { WSG_F32 = 0, WSG_F64 = 1 };
 enum {
     WSG_OK = 0,
     WSG_EINVAL = -1,      /* bad argument (size, precision, null pointer, plan)   */
-    WSG_EWORKSPACE = -2,  /* workspace smaller than grid_workspace_bytes()        */
+    WSG_EWORKSPACE = -2,  /* workspace smaller than grid_workspace_bytes_min()    */
     WSG_ENOMEM = -3,      /* host allocation failed                               */
     WSG_EHIP = -4         /* HIP runtime error (no device, launch failure, ...)   */
 };
@@ -85,20 +85,31 @@ int grid_plan_info(const wsg_plan* plan, int* Nprime, int* t_lo, int* n_layers,
                    double* n0, double* n_scale, double* E);
 
 /*
- * Device workspace (bytes) that one grid_visibilities or degrid_visibilities
- * call with M visibilities at precision `prec` needs: the w-layer stack
- * (n_layers N'^2 complex; only tiles some visibility reaches are touched), the
- * FFT intermediate before and after its transpose (2 n_layers N N' complex),
- * the binned visibility records (2 M records), the degrid per-tile parts
- * (8 M complex) and the bin tables.  0 on a bad argument.
+ * Device workspace (bytes) for one grid_visibilities or degrid_visibilities
+ * call with M visibilities at precision `prec` that holds every w-layer at
+ * once: the w-layer stack (n_layers N'^2 complex; only tiles some visibility
+ * reaches are touched), the FFT intermediate before and after its transpose
+ * (2 n_layers N N' complex), the binned visibility records (2 M records), the
+ * degrid per-tile parts (8 M complex) and the bin tables.  0 on a bad argument.
  */
 size_t grid_workspace_bytes(const wsg_plan* plan, int prec, int64_t M);
+
+/*
+ * Smallest workspace (bytes) a call accepts: the same buffers with the stack
+ * and FFT intermediates sized for one tile layer (16 w-layers).  A call given
+ * ws_bytes between this and grid_workspace_bytes() processes the layers in
+ * passes of as many tile layers as fit (Algorithm 5 steps 3a-4 and Algorithm 6
+ * steps 3-4 are independent per layer; gridding sums the passes' maps, so the
+ * result differs from one pass only by rounding order; degridding is the same
+ * arithmetic).  0 on a bad argument.
+ */
+size_t grid_workspace_bytes_min(const wsg_plan* plan, int prec, int64_t M);
 
 /*
  * Dirty map by Algorithm 5.
  *   uvw   [M][3] float64 device;  vis [M] complex (prec) device;
  *   dirty [N][N] real (prec) device, overwritten;
- *   ws    device workspace of ws_bytes >= grid_workspace_bytes(plan, prec, M),
+ *   ws    device workspace of ws_bytes >= grid_workspace_bytes_min(plan, prec, M),
  *         contents on entry ignored (the call owns it until the stream reaches
  *         the end of the call's work).
  * M = 0 gives an all-zero map (uvw and vis may then be NULL).
@@ -131,8 +142,9 @@ int64_t grid_skipped(const wsg_plan* plan, const void* ws, void* stream);
  *   3 grid FFT pass along u (+ w-screen, sum)    7 degrid 3-D gather tiles
  *   8 grid intermediate transpose                9 degrid intermediate transpose
  * wsg_stage_times() waits for the recorded events, writes the summed
- * milliseconds and launch counts of the first n stages (either pointer may be
- * NULL), clears the record and returns WSG_NSTAGES (or < 0 on error).
+ * milliseconds and the number of timed sections of the first n stages (one per
+ * layer pass; stage 7 one more for the final sum of parts; either pointer may
+ * be NULL), clears the record and returns WSG_NSTAGES (or < 0 on error).
  */
 #define WSG_NSTAGES 10
 void wsg_stage_timing(int enable);

@@ -73,6 +73,9 @@ struct Rec {
 struct DevParams {
     int N, Np, W, n_layers, t_lo;
     int nbr, nbs, nbt;      // bins (= tiles) along r (u), s (v), t (w)
+    // layer pass: layers [pl0, pl0 + pln) (counted from t_lo; pl0 a multiple of
+    // kTileT) sit in the stack and FFT buffers, local layer index t - pl0
+    int pl0, pln;
     double umul;            // l_max / x0: u -> u'
     double nscale;          // w -> w'
     double z0;

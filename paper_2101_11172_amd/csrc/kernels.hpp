@@ -477,8 +477,12 @@ __device__ __forceinline__ int mod_w(int x) {
     return (x + 16 * W) % W;
 }
 
+// The launch covers the tiles of the current layer pass (tile layers
+// pl0 / kTileT onwards); the result is the global tile index.
 __device__ __forceinline__ int tile_of_block(const DevParams& P) {
-    return xcd_interleave<4>(blockIdx.x, P.nbt * P.nbs * P.nbr);
+    const int per_layer = P.nbs * P.nbr;
+    const int nbt_pass = (P.pln + kTileT - 1) / kTileT;
+    return (P.pl0 / kTileT) * per_layer + xcd_interleave<4>(blockIdx.x, nbt_pass * per_layer);
 }
 
 // Kernel weights of one record on the three axes by Horner's rule; the same
@@ -733,7 +737,7 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     // write the tile: rows of kTileS cells
     for (int i = tid; i < nt_valid * kTileR * kTileS; i += 256) {
         const int ss = i % kTileS, rr = (i / kTileS) % kTileR, tt = i / (kTileR * kTileS);
-        stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)] = cpx<R>{tre[i], tim[i]};
+        stack[((size_t)(t0 - P.pl0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)] = cpx<R>{tre[i], tim[i]};
     }
 }
 
@@ -798,7 +802,7 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
         if (c >= 0 && c < G::kCells) {
             const int tt = c / G::kLT, rem = c % G::kLT, rr = rem / G::kLR, ss = rem % G::kLR;
             if (tt < nt_valid && rr < kTileR && ss < kTileS)
-                q = stack[((size_t)(t0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)];
+                q = stack[((size_t)(t0 - P.pl0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)];
         }
         g[i] = q;
     }
@@ -917,7 +921,7 @@ struct FftCfg {
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_grid_fft_a(const cpx<R>* __restrict__ stack, const uint8_t* __restrict__ occ, cpx<R>* __restrict__ inter,
-                 const cpx<R>* __restrict__ tw, int N, int n_layers, int nbr) {
+                 const cpx<R>* __restrict__ tw, int N, int n_layers, int nbr, int t_base) {
     using C = FftCfg<R, LOGN>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size, NG = kTileR / NL;
     static_assert(kTileR % NL == 0, "a row of tiles is a whole number of line groups");
@@ -928,7 +932,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     const int line = threadIdx.x / T, j = threadIdx.x % T;
     cpx<R>* lbuf = buf + line * LP;
     // tile (t / 16, s / 16, rt) holds s = j + T k
-    const uint8_t* orow = occ + (size_t)(t / kTileT) * (Np / kTileS) * nbr + rt;
+    const uint8_t* orow = occ + (size_t)((t + t_base) / kTileT) * (Np / kTileS) * nbr + rt;
     bool on[16], any = false;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -992,13 +996,13 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         z[k] = nm1 / P.nscale + P.z0;                         // (n - n0) / n_scale
         acc[k] = R(0);
     }
-    for (int t = 0; t < P.n_layers; ++t) {
+    for (int t = 0; t < P.pln; ++t) {
         const cpx<R>* src = inter + ((size_t)t * N + qq) * Np;
         cpx<R> v[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) v[k] = src[j + T * k];
         fft_line<R, LOGN, +1>(v, lbuf, tw, j);
-        const double tl = double(t + P.t_lo);
+        const double tl = double(t + P.pl0 + P.t_lo);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (pix[k] >= 0) {
@@ -1009,9 +1013,14 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         }
     }
     if (!row_ok) return;
+    // the first layer pass writes the map, later ones add to it
 #pragma unroll
     for (int k = 0; k < 16; ++k)
-        if (pix[k] >= 0) dirty[(size_t)q * N + pix[k]] = acc[k] * corr[(size_t)q * N + pix[k]];
+        if (pix[k] >= 0) {
+            const size_t o = (size_t)q * N + pix[k];
+            const R d = acc[k] * corr[o];
+            dirty[o] = P.pl0 > 0 ? dirty[o] + d : d;
+        }
 }
 
 // degrid pass B': for each image row q and layer t: f h_x h_y h_z exp(-i 2 pi t z)
@@ -1043,8 +1052,8 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         const double nm1 = -r2 / (1.0 + sqrt(1.0 - r2));
         z[k] = nm1 / P.nscale + P.z0;
     }
-    for (int t = 0; t < P.n_layers; ++t) {
-        const double tl = double(t + P.t_lo);
+    for (int t = 0; t < P.pln; ++t) {
+        const double tl = double(t + P.pl0 + P.t_lo);
         cpx<R> v[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -1070,7 +1079,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_degrid_fft_a(const cpx<R>* __restrict__ inter, const uint8_t* __restrict__ occ, const cpx<R>* __restrict__ tw,
-                   cpx<R>* __restrict__ stack, int N, int n_layers, int nbr) {
+                   cpx<R>* __restrict__ stack, int N, int n_layers, int nbr, int t_base) {
     using C = FftCfg<R, LOGN>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size, NG = kTileR / NL;
     static_assert(kTileR % NL == 0, "a row of tiles is a whole number of line groups");
@@ -1080,7 +1089,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     const int t = lb / rows, rt = lb % rows;
     const int line = threadIdx.x / T, j = threadIdx.x % T;
     cpx<R>* lbuf = buf + line * LP;
-    const uint8_t* orow = occ + (size_t)(t / kTileT) * (Np / kTileS) * nbr + rt;
+    const uint8_t* orow = occ + (size_t)((t + t_base) / kTileT) * (Np / kTileS) * nbr + rt;
     bool on[16], any = false;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -1123,7 +1132,8 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
 // skipped whole).
 template <typename R, int THREADS, bool R_IN>
 __global__ void __launch_bounds__(THREADS) k_transpose(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
-                                                       int A, int B, const uint8_t* __restrict__ rows, int nbr) {
+                                                       int A, int B, const uint8_t* __restrict__ rows, int nbr,
+                                                       int t_base) {
     __shared__ cpx<R> tile[64][65];
     __shared__ uint8_t live[4];
     const int ta_n = (A + 63) / 64, tb_n = (B + 63) / 64;
@@ -1131,7 +1141,8 @@ __global__ void __launch_bounds__(THREADS) k_transpose(const cpx<R>* __restrict_
     const int t = lb / (ta_n * tb_n), rem = lb % (ta_n * tb_n);
     const int a0 = (rem / tb_n) * 64, b0 = (rem % tb_n) * 64;
     const int r0 = R_IN ? a0 : b0;
-    if (threadIdx.x < 4) live[threadIdx.x] = rows[(t / kTileT) * nbr + min(r0 / kTileR + int(threadIdx.x), nbr - 1)];
+    if (threadIdx.x < 4)
+        live[threadIdx.x] = rows[((t + t_base) / kTileT) * nbr + min(r0 / kTileR + int(threadIdx.x), nbr - 1)];
     __syncthreads();
     if (!R_IN && !(live[0] | live[1] | live[2] | live[3])) return;
     const cpx<R>* src = in + (size_t)t * A * B;

@@ -94,15 +94,18 @@ namespace {
 struct Layout {
     size_t stack, inter, inter2, rec, rec2, part, count, start, cursor, bsums, cls, occ, rows, skipped, total;
     int nbins, nscan;
+    int pass_layers;   // w-layers held in the stack and FFT buffers at a time (a multiple of kTileT, or all)
 };
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout layout_of(const wsg_plan* p, int prec, int64_t M) {
+// Workspace for passes of `tiles_per_pass` tile layers (kTileT w-layers each).
+Layout layout_of(const wsg_plan* p, int prec, int64_t M, int tiles_per_pass) {
     Layout L{};
     const size_t cs = prec == WSG_F32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
     const size_t rs = prec == WSG_F32 ? sizeof(Rec<float>) : sizeof(Rec<double>);
-    const size_t Np = size_t(p->pp.Nprime), N = size_t(p->pp.N), nl = size_t(p->pp.n_layers());
+    L.pass_layers = std::min(p->pp.n_layers(), std::max(1, std::min(tiles_per_pass, p->nbt)) * kTileT);
+    const size_t Np = size_t(p->pp.Nprime), N = size_t(p->pp.N), nl = size_t(L.pass_layers);
     L.nbins = p->nbins();
     L.nscan = (L.nbins + 1023) / 1024;
     // the skipped counter sits at offset 0 whatever M and the precision
@@ -135,6 +138,8 @@ DevParams dev_params(const wsg_plan* p) {
     P.nbr = p->nbr;
     P.nbs = p->nbs;
     P.nbt = p->nbt;
+    P.pl0 = 0;
+    P.pln = p->pp.n_layers();
     P.umul = p->pp.l_max / p->pp.x0;
     P.nscale = p->pp.n_scale;
     P.z0 = p->pp.x0;
@@ -192,11 +197,13 @@ template <typename R>
 void transpose(const DevParams& P, const cpx<R>* in, cpx<R>* out, int A, int B, bool r_in, const uint8_t* rows,
                hipStream_t s) {
     constexpr int TH = 512;
-    const unsigned blocks = unsigned(P.n_layers) * unsigned((A + 63) / 64) * unsigned((B + 63) / 64);
+    const unsigned blocks = unsigned(P.pln) * unsigned((A + 63) / 64) * unsigned((B + 63) / 64);
     if (r_in)
-        hipLaunchKernelGGL((k_transpose<R, TH, true>), dim3(blocks), dim3(TH), 0, s, in, out, A, B, rows, P.nbr);
+        hipLaunchKernelGGL((k_transpose<R, TH, true>), dim3(blocks), dim3(TH), 0, s, in, out, A, B, rows, P.nbr,
+                           P.pl0);
     else
-        hipLaunchKernelGGL((k_transpose<R, TH, false>), dim3(blocks), dim3(TH), 0, s, in, out, A, B, rows, P.nbr);
+        hipLaunchKernelGGL((k_transpose<R, TH, false>), dim3(blocks), dim3(TH), 0, s, in, out, A, B, rows, P.nbr,
+                           P.pl0);
 }
 
 template <typename R, int LOGN>
@@ -204,13 +211,13 @@ void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, const uint8
                   cpx<R>* inter2,
                   const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
     using C = FftCfg<R, LOGN>;
-    const unsigned grid_a = unsigned(P.n_layers) * unsigned(C::N / kTileR);
+    const unsigned grid_a = unsigned(P.pln) * unsigned(C::N / kTileR);
     const unsigned grid_b = unsigned((P.N + C::kNLr - 1) / C::kNLr);
     if (grid) {
         {
             StageMark mark(s, 2);
             hipLaunchKernelGGL((k_grid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
-                               (const cpx<R>*)stack, occ, inter, tw, P.N, P.n_layers, P.nbr);
+                               (const cpx<R>*)stack, occ, inter, tw, P.N, P.pln, P.nbr, P.pl0);
         }
         {
             StageMark mark(s, 8);
@@ -231,7 +238,7 @@ void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, const uint8
         }
         StageMark mark(s, 6);
         hipLaunchKernelGGL((k_degrid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
-                           (const cpx<R>*)inter2, occ, tw, stack, P.N, P.n_layers, P.nbr);
+                           (const cpx<R>*)inter2, occ, tw, stack, P.N, P.pln, P.nbr, P.pl0);
     }
 }
 
@@ -259,9 +266,12 @@ int check_call(const wsg_plan* plan, int prec, int64_t M, const double* uvw, con
     if (!a && (M > 0 || !a_empty_ok)) return fail(WSG_EINVAL, "null visibility/image pointer");
     if (!b && (M > 0 || !b_empty_ok)) return fail(WSG_EINVAL, "null output pointer");
     if (!ws) return fail(WSG_EINVAL, "null workspace");
-    *L = layout_of(plan, prec, M);
+    // as many tile layers per pass as the workspace holds
+    int tiles = plan->nbt;
+    *L = layout_of(plan, prec, M, tiles);
+    while (tiles > 1 && ws_bytes < L->total) *L = layout_of(plan, prec, M, --tiles);
     if (ws_bytes < L->total)
-        return fail(WSG_EWORKSPACE, "workspace too small: need " + std::to_string(L->total) + " bytes");
+        return fail(WSG_EWORKSPACE, "workspace too small: need at least " + std::to_string(L->total) + " bytes");
     int dev = -1;
     WSG_HIP(hipGetDevice(&dev));
     if (dev != plan->device) return fail(WSG_EINVAL, "plan was created on another device");
@@ -316,26 +326,41 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
         hipLaunchKernelGGL(k_tile_occupancy, dim3((L.nbins + 255) / 256), dim3(256), 0, s, (const uint32_t*)start,
                            (const uint32_t*)cls, P, occ, rows);
     }
-    if (grid) {
-        {
-            StageMark mark(s, 1);
-            launch_tiles<R>(true, P.W, L.nbins, rec, start, cls, occ, P, coef, stack, nullptr, 0, s);
+    // Layer passes: the stack and FFT buffers hold L.pass_layers layers at a
+    // time.  Grid: each pass scatters into its tiles and transforms them; the
+    // first pass writes the dirty map, later ones add to it.  Degrid: each pass
+    // transforms its layers and gathers from its tiles; every (visibility, tile)
+    // part belongs to exactly one pass, and k_degrid_finish sums them at the end.
+    const int per_layer = P.nbs * P.nbr;
+    auto* part = reinterpret_cast<cpx<R>*>(w + L.part);
+    for (int pl0 = 0; pl0 < P.n_layers; pl0 += L.pass_layers) {
+        DevParams Q = P;
+        Q.pl0 = pl0;
+        Q.pln = std::min(L.pass_layers, P.n_layers - pl0);
+        const int nblocks = ((Q.pln + kTileT - 1) / kTileT) * per_layer;
+        if (grid) {
+            {
+                StageMark mark(s, 1);
+                launch_tiles<R>(true, P.W, nblocks, rec, start, cls, occ, Q, coef, stack, nullptr, 0, s);
+            }
+            launch_fft<R>(true, plan->log2_np, Q, occ, rows, stack, inter, inter2, tw, corr, nullptr,
+                          static_cast<R*>(out), s);
+        } else {
+            launch_fft<R>(false, plan->log2_np, Q, occ, rows, stack, inter, inter2, tw, corr,
+                          static_cast<const R*>(in), nullptr, s);
+            if (M > 0) {
+                StageMark mark(s, 7);
+                launch_tiles<R>(false, P.W, nblocks, rec, start, cls, occ, Q, coef, stack, part, size_t(M), s);
+            }
         }
-        launch_fft<R>(true, plan->log2_np, P, occ, rows, stack, inter, inter2, tw, corr, nullptr, static_cast<R*>(out),
-                      s);
-    } else {
-        launch_fft<R>(false, plan->log2_np, P, occ, rows, stack, inter, inter2, tw, corr, static_cast<const R*>(in),
-                      nullptr,
-                      s);
+    }
+    if (!grid) {
         fill<R>(static_cast<R*>(out), size_t(2 * M), R(0), s);     // skipped visibilities stay zero
         StageMark mark(s, 7);
-        if (M > 0) {
-            auto* part = reinterpret_cast<cpx<R>*>(w + L.part);
-            launch_tiles<R>(false, P.W, L.nbins, rec, start, cls, occ, P, coef, stack, part, size_t(M), s);
+        if (M > 0)
             hipLaunchKernelGGL(k_degrid_finish<R>, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s,
                                (const Rec<R>*)rec, (const uint32_t*)(start + L.nbins), (const cpx<R>*)part,
                                size_t(M), P.W, static_cast<cpx<R>*>(out));
-        }
     }
     WSG_HIP(hipGetLastError());
     return WSG_OK;
@@ -537,7 +562,12 @@ int grid_plan_info(const wsg_plan* plan, int* Nprime, int* t_lo, int* n_layers, 
 
 size_t grid_workspace_bytes(const wsg_plan* plan, int prec, int64_t M) {
     if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL) return 0;
-    return layout_of(plan, prec, M).total;
+    return layout_of(plan, prec, M, plan->nbt).total;
+}
+
+size_t grid_workspace_bytes_min(const wsg_plan* plan, int prec, int64_t M) {
+    if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL) return 0;
+    return layout_of(plan, prec, M, 1).total;
 }
 
 int grid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* vis, void* dirty,

@@ -29,6 +29,7 @@ _SIGNATURES = {
     "grid_plan_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, _c_int_p, _c_int_p, _c_double_p, _c_double_p,
                                       _c_double_p]),
     "grid_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]),
+    "grid_workspace_bytes_min": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]),
     "grid_visibilities": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                          ctypes.c_void_p]),
@@ -101,6 +102,13 @@ def grid_workspace_bytes(plan: int, prec: int, M: int) -> int:
     return n
 
 
+def grid_workspace_bytes_min(plan: int, prec: int, M: int) -> int:
+    n = lib().grid_workspace_bytes_min(plan, prec, M)
+    if n == 0:
+        raise RuntimeError("grid_workspace_bytes_min: bad argument")
+    return n
+
+
 def grid_visibilities(plan: int, prec: int, M: int, uvw_ptr: int, vis_ptr: int, dirty_ptr: int,
                       ws_ptr: int, ws_bytes: int, stream: int) -> None:
     _err(lib().grid_visibilities(plan, prec, M, uvw_ptr, vis_ptr, dirty_ptr, ws_ptr, ws_bytes, stream),
@@ -169,9 +177,15 @@ _PREC = {torch.complex64: WSG_F32, torch.complex128: WSG_F64, torch.float32: WSG
 
 
 class Plan:
-    """Improved W-stacking plan on one HIP device (see include/wsgrid.h)."""
+    """Improved W-stacking plan on one HIP device (see include/wsgrid.h).
 
-    def __init__(self, N: int, L: float, W: int, x0: float, wmax: float, device=None):
+    max_workspace_bytes caps the workspace each precision allocates: below
+    grid_workspace_bytes the library takes the w-layers in passes (at least
+    grid_workspace_bytes_min is allocated).
+    """
+
+    def __init__(self, N: int, L: float, W: int, x0: float, wmax: float, device=None,
+                 max_workspace_bytes: int | None = None):
         if not torch.cuda.is_available():
             raise RuntimeError("wsgrid needs a HIP device")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
@@ -179,6 +193,7 @@ class Plan:
         with torch.cuda.device(self.device):
             self._p = grid_create(N, L, W, x0, wmax)
         self.N, self.L, self.W, self.x0, self.wmax = N, L, W, x0, wmax
+        self.max_workspace_bytes = max_workspace_bytes
         self.info = grid_plan_info(self._p)
         self._ws = {}
 
@@ -195,6 +210,8 @@ class Plan:
 
     def workspace(self, prec: int, M: int) -> torch.Tensor:
         need = grid_workspace_bytes(self._p, prec, M)
+        if self.max_workspace_bytes is not None and need > self.max_workspace_bytes:
+            need = max(grid_workspace_bytes_min(self._p, prec, M), int(self.max_workspace_bytes))
         ws = self._ws.get(prec)
         if ws is None or ws.numel() < need:
             self._ws.pop(prec, None)

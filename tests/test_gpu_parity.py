@@ -223,3 +223,49 @@ def test_binning_table_overflow():
     assert op.Nprime == 1024 and 16 < op.n_layers <= 32
     uvw = inputs.uniform_uvw(40000, 0.95 * N / (2 * L), wmax, 41)
     _check_both(N, L, W, x0, wmax, uvw, inputs.random_vis(40000, 42), inputs.random_image(N, 43))
+
+
+def test_layer_passes():
+    """112 w-layers (7 tile layers) taken in passes: with the smallest workspace
+    (one tile layer per pass) and with room for three (passes of 48, 48 and 16
+    layers).  Both match the oracle; degridding is the same arithmetic as in
+    one pass (bit-identical), gridding differs from one pass only by the order
+    in which the passes' maps are summed."""
+    N, L, W, x0, wmax, M = 128, 0.8, 7, 0.25, 300.0, 6000
+    op, lm = make_plan(N, L, W, x0, wmax), least_misfit(W, x0)
+    assert op.Nprime == 256 and op.n_layers == 112
+    uvw = inputs.uniform_uvw(M, 0.95 * N / (2 * L), wmax, 61)
+    vis, img = inputs.random_vis(M, 62), inputs.random_image(N, 63)
+    ref_g = wstack.grid(op, lm, uvw, vis)
+    ref_d = wstack.degrid(op, lm, uvw, img)
+    one = plan_for(N, L, W, x0, wmax)
+    single = {prec: (gpu_grid(one, uvw, vis, prec), gpu_degrid(one, uvw, img, prec)) for prec in (64, 32)}
+    for prec, tol in ((64, 1e-10), (32, 1e-6)):
+        code = wg.WSG_F64 if prec == 64 else wg.WSG_F32
+        full = wg.grid_workspace_bytes(one._p, code, M)
+        least = wg.grid_workspace_bytes_min(one._p, code, M)
+        per_tile_layer = (full - least) // 6
+        assert least < full and (full - least) % 6 == 0
+        for cap in (least, least + 2 * per_tile_layer):
+            plan = wg.Plan(N, L, W, x0, wmax, device=DEV, max_workspace_bytes=cap)
+            g = gpu_grid(plan, uvw, vis, prec)
+            d = gpu_degrid(plan, uvw, img, prec)
+            assert plan.workspace(code, M).numel() == cap
+            plan.close()
+            assert rel(g, ref_g) <= tol, (prec, cap, "grid", rel(g, ref_g))
+            assert rel(d, ref_d) <= tol, (prec, cap, "degrid", rel(d, ref_d))
+            assert np.array_equal(d, single[prec][1]), (prec, cap)
+            assert rel(g, single[prec][0]) <= (1e-14 if prec == 64 else 1e-6), (prec, cap)
+
+
+def test_workspace_below_minimum_is_rejected():
+    N, L, W, x0, wmax, M = 128, 0.8, 7, 0.25, 300.0, 100
+    plan = plan_for(N, L, W, x0, wmax)
+    least = wg.grid_workspace_bytes_min(plan._p, wg.WSG_F32, M)
+    ws = torch.empty(least - 256, dtype=torch.uint8, device=DEV)
+    uvw = torch.zeros((M, 3), dtype=torch.float64, device=DEV)
+    vis = torch.zeros(M, dtype=torch.complex64, device=DEV)
+    out = torch.empty((N, N), dtype=torch.float32, device=DEV)
+    with pytest.raises(RuntimeError, match="workspace too small"):
+        wg.grid_visibilities(plan._p, wg.WSG_F32, M, uvw.data_ptr(), vis.data_ptr(), out.data_ptr(),
+                             ws.data_ptr(), ws.numel(), torch.cuda.current_stream(DEV).cuda_stream)
