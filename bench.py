@@ -37,10 +37,9 @@ def workload_stats(uvw, N: int, L: float, W: int, x0: float, wmax: float, Np: in
 
     A visibility's first support index per axis is floor(xi + W/2) - W + 1 with
     xi = (l_max / x0) u, (l_max / x0) v, n_scale w after the Hermitian fold;
-    bins are 16^3 tiles of the stack.  A tile is occupied when its own bin or
-    one of the seven bins one tile back holds a visibility (what the library
-    writes and reads); a visibility visits 1 + [first index in tile >= 17 - W]
-    tiles per axis.
+    bins are 16^3 tiles of the stack.  A tile is occupied when some visibility
+    reaches it (what the library writes and reads); a visibility visits
+    1 + [first index in tile >= 17 - W] tiles per axis.
     """
     import numpy as np
 
@@ -226,6 +225,86 @@ def timed(step, steps: int):
     return (t1 - t0) * 1e3 / steps, wsgrid.wsg_stage_times()
 
 
+def imaging_main(args) -> int:
+    """One gradient step of ||degrid(I) - V||^2 per step: DegridFn forward
+    (degrid_visibilities) and backward (grid_visibilities) on a 4096^2 FP32
+    image with 50,003,456 visibilities (128 antennas in a 10 km-radius disc,
+    +-2 h tracks of 6,152 dumps, declination -30 deg, uvw scaled to a
+    Nyquist-sampled image, L = 0.5), W = 7, x0 = 0.25: N' = 8192, 223 w-layers
+    taken in passes within the workspace cap."""
+    import numpy as np
+    import torch
+
+    from paper_2101_11172_amd import inputs, wsgrid
+
+    dev = torch.device("cuda", 0)
+    N, L, W, x0 = 4096, 0.5, 7, 0.25
+    log("generating the imaging workload")
+    uvw = inputs.scale_to_image(inputs.array_uvw(128, 10000.0, -30.0, -30.0, 2.0, 6152, 1.4e9, 4), N, L)
+    wmax = float(np.max(np.abs(uvw[:, 2])))
+    M = uvw.shape[0]
+    t_uvw = torch.from_numpy(uvw).to(dev)
+    del uvw
+    V = torch.from_numpy(inputs.random_vis(M, 5, np.complex64)).to(dev)
+    cap = int(args.max_workspace_gb * (1 << 30))
+    plan = wsgrid.Plan(N, L, W, x0, wmax, device=dev, max_workspace_bytes=cap)
+    info = plan.info
+    img = torch.nn.Parameter(torch.from_numpy(inputs.random_image(N, 6).astype(np.float32)).to(dev))
+    log(f"M={M} N={N} N'={info['Nprime']} layers={info['n_layers']}")
+
+    def step():
+        loss = torch.sum(torch.abs(wsgrid.degrid_fn(plan, t_uvw, img) - V) ** 2)
+        img.grad = None
+        loss.backward()
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    full = wsgrid.grid_workspace_bytes(plan._p, wsgrid.WSG_F32, M)
+    least = wsgrid.grid_workspace_bytes_min(plan._p, wsgrid.WSG_F32, M)
+    per_tile_layer = (full - least) // max(1, (info["n_layers"] + 15) // 16 - 1)
+    tiles_per_pass = 1 + (plan.workspace(wsgrid.WSG_F32, M).numel() - least) // per_tile_layer
+    passes = -(-((info["n_layers"] + 15) // 16) // tiles_per_pass)
+    ms, _ = timed(step, args.steps)
+    log(f"imaging: {ms:.3f} ms/step, {M / (ms * 1e-3):.4e} vis/s, {passes} layer passes")
+    # stage breakdown from the same two calls made on this thread (autograd runs
+    # the backward on a thread of its own, where stage timing is not enabled)
+    vis = torch.empty(M, dtype=torch.complex64, device=dev)
+    grad = torch.empty((N, N), dtype=torch.float32, device=dev)
+
+    def direct():
+        plan.degrid(t_uvw, img.detach(), out=vis)
+        plan.grid(t_uvw, vis, out=grad)
+
+    ms_direct, stages = timed(direct, args.steps)
+    result = {
+        "metric": "differentiable imaging: visibilities/s per gradient step (degrid forward + grid backward)",
+        "value": M / (ms * 1e-3),
+        "unit": "visibilities/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"differentiable imaging: {N}x{N} FP32 image parameter, L={L}, W={W}, x0={x0}, "
+                                f"{M} visibilities (128 antennas in a 10 km disc, +-2 h tracks, dec -30, uvw "
+                                f"scaled to a Nyquist-sampled image), {info['n_layers']} w-layers, "
+                                f"N'={info['Nprime']}, {passes} layer passes"),
+                   "N": N, "L": L, "visibilities": M, "w_layers": info["n_layers"], "fft_size": info["Nprime"],
+                   "workspace_bytes": plan.workspace(wsgrid.WSG_F32, M).numel(), "layer_passes": passes},
+        "direct_calls_ms_per_step": ms_direct,
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+    }
+    print(json.dumps(result), flush=True)
+    plan.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,11 +316,16 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=60000)
     ap.add_argument("--copy-gb", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GB (counter calibration)")
+    ap.add_argument("--workload", choices=("widefield", "imaging"), default="widefield",
+                    help="imaging: one differentiable-imaging gradient step per step (4096^2, 50M visibilities)")
+    ap.add_argument("--max-workspace-gb", type=float, default=96.0, help="imaging: workspace cap (layer passes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path is built and measured on a single MI355X "
               "(multi-GPU sharding over w-layers is a design, not a measured run)", file=sys.stderr)
         return 2
+    if args.workload == "imaging":
+        return imaging_main(args)
 
     import numpy as np
     import torch
