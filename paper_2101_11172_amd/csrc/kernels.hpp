@@ -907,9 +907,9 @@ struct FftCfg {
     static constexpr int kNLt0 = (80 * 1024 - 2048) / kLineBytes;
     static constexpr int kNLt1 = kNLt0 < 1 ? 1 : kNLt0;
     static constexpr int kNLt2 = kNLt1 >= 16 ? 16 : kNLt1 >= 8 ? 8 : kNLt1 >= 4 ? 4 : kNLt1 >= 2 ? 2 : 1;
-    static constexpr int kNLt = (kNLt2 * T > 1024) ? 1024 / T : kNLt2;   // a power of two
     // lines per block for the row passes: at least 256 threads
     static constexpr int kNLr = (T >= 256) ? 1 : 256 / T;
+    static constexpr int kNLt = kNLr < 16 ? kNLr : 16;
 };
 
 // grid pass A: IFFT along s of stack rows [t][r][:], keep image rows q, write
