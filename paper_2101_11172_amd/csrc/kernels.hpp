@@ -77,7 +77,7 @@ __device__ __forceinline__ int bin_of(const VisCoords& c, const DevParams& P) {
 // probing) before one global update per distinct bin; a visibility whose bin
 // finds no table slot updates the global counter directly.
 constexpr int kAggThreads = 1024;
-constexpr int kAggPer = 32;
+constexpr int kAggPer = 8;
 constexpr int kAggChunk = kAggThreads * kAggPer;
 constexpr int kAggSlots = 4096;
 constexpr int kAggProbes = 32;
