@@ -9,6 +9,11 @@ Test infrastructure: see ``oracle/__init__.py``.
 * z = (n - n0) / n_scale on the sphere (eq. z-on-sphere), with
   n_scale = (1 - n_min) / (2 z0) and n0 = 1 - z0 n_scale (eq. n_params),
   n_min = sqrt(1 - l_max^2 - m_max^2), and z0 = x0 (Sec. 6.2 recommendation).
+  Then z runs from -z0 (map corners) to +z0 (centre).  The variant without z
+  offset (Sec. 5.3, eq. n_params_no_offset) takes n_scale = (1 - n_min) / z0
+  and n0 = 1, so that z runs from -z0 to 0 and z = 0 at the map centre, at
+  about twice the number of layers.  In both, z = (n - 1) / n_scale + z_shift
+  with z_shift = (1 - n0) / n_scale (z0, or 0 without offset).
 * w-layers at w[t] = t / n_scale (Algorithm 5 step 1).  After the Hermitian fold
   (Sec. 5.4) w >= 0, so w' = n_scale w lies in [0, n_scale w_max].  With the
   support convention of ``wstack.support`` a visibility at w' touches layers
@@ -42,6 +47,7 @@ class Plan:
     n0: float
     t_lo: int
     t_hi: int
+    z_offset: bool = True
 
     @property
     def n_layers(self) -> int:
@@ -50,6 +56,11 @@ class Plan:
     @property
     def z0(self) -> float:
         return self.x0
+
+    @property
+    def z_shift(self) -> float:
+        """(1 - n0) / n_scale: z0 with the z offset, 0 without."""
+        return self.z0 if self.z_offset else 0.0
 
     def pixel_lm(self):
         """Direction cosines of pixel columns (l) / rows (m): (i - N/2) L / N."""
@@ -69,11 +80,11 @@ class Plan:
 
     def z(self):
         """z = (n - n0) / n_scale on the [m, l] pixel grid (eq. z-on-sphere)."""
-        # n - n0 = (n - 1) + (1 - n0) = (n - 1) + z0 n_scale
-        return self.n_minus_1() / self.n_scale + self.z0
+        # n - n0 = (n - 1) + (1 - n0) = (n - 1) + z_shift n_scale
+        return self.n_minus_1() / self.n_scale + self.z_shift
 
 
-def make_plan(N: int, L: float, W: int, x0: float, wmax: float) -> Plan:
+def make_plan(N: int, L: float, W: int, x0: float, wmax: float, z_offset: bool = True) -> Plan:
     if N <= 0 or N % 2:
         raise ValueError("N must be positive and even")
     if not (0.0 < x0 <= 0.5):
@@ -90,12 +101,16 @@ def make_plan(N: int, L: float, W: int, x0: float, wmax: float) -> Plan:
     l_max = 0.5 * L
     n_min = math.sqrt(1.0 - 2.0 * l_max * l_max)
     z0 = x0
-    n_scale = (1.0 - n_min) / (2.0 * z0)          # eq. n_params
-    n0 = 1.0 - z0 * n_scale
+    if z_offset:
+        n_scale = (1.0 - n_min) / (2.0 * z0)      # eq. n_params
+        n0 = 1.0 - z0 * n_scale
+    else:
+        n_scale = (1.0 - n_min) / z0              # eq. n_params_no_offset
+        n0 = 1.0
     t_lo = W // 2 - W + 1
     t_hi = int(math.floor(n_scale * wmax + 0.5 * W))
     return Plan(N=N, L=L, W=W, x0=x0, wmax=wmax, Nprime=int(round(Np)), l_max=l_max,
-                n_min=n_min, n_scale=n_scale, n0=n0, t_lo=t_lo, t_hi=t_hi)
+                n_min=n_min, n_scale=n_scale, n0=n0, t_lo=t_lo, t_hi=t_hi, z_offset=z_offset)
 
 
 def layers_required(dn_dw: float, z0: float, W: int) -> int:

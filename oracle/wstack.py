@@ -92,8 +92,8 @@ def grid_prepare(plan: Plan, lm: LeastMisfit, uvw, vis) -> GridInput:
     keep = uvw_f[:, 2] <= plan.wmax
     uvw_f, V = uvw_f[keep], V[keep]
     up, vp, wp = _normalised(plan, uvw_f)
-    # n0 - 1 = -z0 n_scale (eq. n_params)
-    Vh = V * np.exp(2j * np.pi * uvw_f[:, 2] * (-plan.z0 * plan.n_scale))
+    # n0 - 1 = -z_shift n_scale (eq. n_params; 0 without z offset)
+    Vh = V * np.exp(2j * np.pi * uvw_f[:, 2] * (-plan.z_shift * plan.n_scale))
     t_first, cz = _weights(lm, wp, W)
     r_first, cx = _weights(lm, up, W)
     s_first, cy = _weights(lm, vp, W)
@@ -175,7 +175,7 @@ def degrid_correlate(plan: Plan, lm: LeastMisfit, uvw, stack: np.ndarray) -> np.
         vals = stack[tt[:, :, None, None], ss[:, None, :, None], rr[:, None, None, :]]
         wgt = cz[:, :, None, None] * cy[:, None, :, None] * cx[:, None, None, :]
         acc = np.sum(vals * wgt, axis=(1, 2, 3))
-        acc = acc * np.exp(-2j * np.pi * uvw_f[k, 2] * (-plan.z0 * plan.n_scale))
+        acc = acc * np.exp(-2j * np.pi * uvw_f[k, 2] * (-plan.z_shift * plan.n_scale))
         out[k] = np.where(neg[k], np.conj(acc), acc)
     return out
 

@@ -66,3 +66,18 @@ def test_tiny_workload_layers():
 def test_invalid_plans(args):
     with pytest.raises(ValueError):
         make_plan(*args)
+
+
+def test_no_offset_variant():
+    # Sec. 5.3, eq. n_params_no_offset: n0 = 1, n_scale = (1 - n_min) / z0, so
+    # z = 0 at the map centre and -z0 at the corners, twice the layer spacing rate
+    p = make_plan(256, 0.4, 7, 0.25, 100.0)
+    q = make_plan(256, 0.4, 7, 0.25, 100.0, z_offset=False)
+    assert q.n0 == 1.0 and q.n_scale == 2.0 * p.n_scale and q.z_shift == 0.0
+    z = q.z()
+    assert z[128, 128] == 0.0
+    assert abs(z[0, 0] + 0.25) < 1e-12
+    assert z.max() == 0.0 and z.min() >= -0.25 - 1e-12
+    # layers: floor(n_scale w_max + W/2) at the doubled n_scale
+    assert q.t_lo == p.t_lo and q.t_hi == int(math.floor(q.n_scale * 100.0 + 3.5))
+    assert q.n_layers > p.n_layers

@@ -139,3 +139,24 @@ def test_planted_mistakes_are_caught(monkeypatch):
 
     # (4) l and m transposed
     assert rel(wstack.grid(p, lm, uvw, V), exact.T) > 100 * bound
+
+
+def test_no_offset_variant_matches_dft():
+    # Sec. 5.3 variant (eq. n_params_no_offset): same method, z in [-z0, 0]
+    uvw = uniform_uvw(300, 0.9 * 64 / (2 * 0.3), 100.0, 21)
+    V = random_vis(300, 22)
+    lm = least_misfit(7, 0.25)
+    p = make_plan(64, 0.3, 7, 0.25, 100.0, z_offset=False)
+    q = make_plan(64, 0.3, 7, 0.25, 100.0)
+    bound = 2 * np.sqrt(3) * lm.E
+    g, exact = wstack.grid(p, lm, uvw, V), dft.dft_grid(p, uvw, V)
+    f = random_image(64, 23)
+    d = wstack.degrid(p, lm, uvw, f)
+    assert rel(g, exact) <= bound and rel(d, dft.dft_degrid(p, uvw, f)) <= bound
+    # a different approximation from the offset plan's, both near the DFT
+    assert rel(g, wstack.grid(q, lm, uvw, V)) > 1e-3 * lm.E
+    lhs = np.real(np.vdot(V, d))
+    assert abs(lhs - float(np.sum(f * g))) <= 1e-12 * abs(lhs)
+    # planted: an offset plan's per-visibility phase exp[i 2 pi w (n0 - 1)] left in
+    Vbad = V * np.exp(2j * np.pi * np.abs(uvw[:, 2]) * (-0.25 * p.n_scale))
+    assert rel(wstack.grid(p, lm, uvw, Vbad), exact) > 100 * bound
