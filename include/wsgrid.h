@@ -74,6 +74,18 @@ enum {
  */
 wsg_plan* grid_create(int N, double L, int W, double x0, double wmax);
 
+/*
+ * As grid_create, choosing the placement of the z = 0 plane (Sec. 5.3).
+ * z_offset != 0: eq. n_params, exactly grid_create (z in [-z0, z0], the fewest
+ * layers).  z_offset == 0: the variant without z offset, eq.
+ * n_params_no_offset: n_scale = (1 - n_min) / z0 and n0 = 1, so z = 0 at the
+ * map centre, where the correction h_z is smallest, and z in [-z0, 0]; the
+ * layer spacing in w halves, so about twice as many layers, and the
+ * per-visibility phase exp(+-i 2 pi w (n0 - 1)) is 1.  Same ranges, errors and
+ * ownership as grid_create.
+ */
+wsg_plan* grid_create_variant(int N, double L, int W, double x0, double wmax, int z_offset);
+
 /* Free a plan and its device tables (blocking).  NULL is ignored. */
 void grid_destroy(wsg_plan* plan);
 
@@ -164,10 +176,11 @@ int wsg_design_eval(int W, double x0, int n_nu, const double* nu, double* c_out,
                     int n_x, const double* x, double* h_out, double* E_out);
 
 /*
- * Host-only planner (no GPU use): the values grid_create would use.
+ * Host-only planner (no GPU use): the values grid_create_variant(..., z_offset)
+ * would use (z_offset = 1: grid_create).  Any output pointer may be NULL.
  */
-int wsg_plan_params(int N, double L, int W, double x0, double wmax, int* Nprime,
-                    int* t_lo, int* t_hi, double* n0, double* n_scale);
+int wsg_plan_params(int N, double L, int W, double x0, double wmax, int z_offset,
+                    int* Nprime, int* t_lo, int* t_hi, double* n0, double* n_scale);
 
 #ifdef __cplusplus
 }

@@ -81,7 +81,7 @@ struct DevParams {
     int pl0, pln;
     double umul;            // l_max / x0: u -> u'
     double nscale;          // w -> w'
-    double z0;
+    double zshift;          // (1 - n0) / n_scale: z = (n - 1) / n_scale + zshift
     double wmax;
     double dl;              // pixel size L / N
 };

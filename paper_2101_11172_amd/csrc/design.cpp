@@ -447,7 +447,7 @@ KernelDesign design_kernel(int W, double x0) {
     return D;
 }
 
-std::string make_plan_params(int N, double L, int W, double x0, double wmax, PlanParams* p) {
+std::string make_plan_params(int N, double L, int W, double x0, double wmax, PlanParams* p, bool z_offset) {
     if (N <= 0 || (N & 1)) return "N must be positive and even";
     if (!(x0 > 0.0 && x0 <= 0.5)) return "x0 must be in (0, 1/2]";
     if (W < 1 || W > 16) return "W must be in [1, 16]";
@@ -464,8 +464,16 @@ std::string make_plan_params(int N, double L, int W, double x0, double wmax, Pla
     p->Nprime = int(npr);
     p->l_max = 0.5 * L;
     p->n_min = std::sqrt(1.0 - 2.0 * p->l_max * p->l_max);
-    p->n_scale = (1.0 - p->n_min) / (2.0 * x0);     // eq. n_params with z0 = x0
-    p->n0 = 1.0 - x0 * p->n_scale;
+    p->z_offset = z_offset;
+    if (z_offset) {
+        p->n_scale = (1.0 - p->n_min) / (2.0 * x0);     // eq. n_params with z0 = x0
+        p->n0 = 1.0 - x0 * p->n_scale;
+        p->z_shift = x0;
+    } else {
+        p->n_scale = (1.0 - p->n_min) / x0;             // eq. n_params_no_offset
+        p->n0 = 1.0;
+        p->z_shift = 0.0;
+    }
     p->t_lo = W / 2 - W + 1;
     double top = std::floor(p->n_scale * wmax + 0.5 * W);
     if (top > 1e6) return "wmax too large: more than a million w-layers";

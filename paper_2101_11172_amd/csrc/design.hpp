@@ -36,11 +36,15 @@ KernelDesign design_kernel(int W, double x0);
 struct PlanParams {
     int N = 0, W = 0, Nprime = 0, t_lo = 0, t_hi = 0;
     double L = 0, x0 = 0, wmax = 0, l_max = 0, n_min = 0, n_scale = 0, n0 = 0;
+    bool z_offset = true;
+    double z_shift = 0;     // (1 - n0) / n_scale: z = (n - 1) / n_scale + z_shift
     int n_layers() const { return t_hi - t_lo + 1; }
 };
 
 // Validates and fills the plan parameters; returns an empty string on success,
 // else the reason.
-std::string make_plan_params(int N, double L, int W, double x0, double wmax, PlanParams* p);
+// z_offset selects eq. n_params (z in [-z0, z0]) or, when false, the variant
+// without z offset, eq. n_params_no_offset (n0 = 1, z in [-z0, 0]; Sec. 5.3).
+std::string make_plan_params(int N, double L, int W, double x0, double wmax, PlanParams* p, bool z_offset = true);
 
 }  // namespace wsg

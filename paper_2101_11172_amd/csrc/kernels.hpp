@@ -211,7 +211,8 @@ __global__ void k_scan_add(uint32_t* __restrict__ out, int n, const uint32_t* __
         if (base + i < n) out[base + i] += add;
 }
 
-// grid: v = V exp(+i 2 pi w (n0 - 1)) with n0 - 1 = -z0 n_scale (eq. n_params),
+// grid: v = V exp(+i 2 pi w (n0 - 1)) with n0 - 1 = -zshift n_scale (eq. n_params:
+// zshift = z0; zero without z offset, eq. n_params_no_offset),
 // V conjugated for a folded visibility.  degrid: v = exp(-i 2 pi w (n0 - 1)).
 template <typename R, bool GRID>
 __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __restrict__ uvw,
@@ -254,7 +255,7 @@ __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __res
         r.nu[0] = R(c.nu_u);
         r.nu[1] = R(c.nu_v);
         r.nu[2] = R(c.nu_w);
-        double turns = c.w * (-P.z0 * P.nscale);     // w (n0 - 1)
+        double turns = c.w * (-P.zshift * P.nscale);     // w (n0 - 1)
         double sn, co;
         phase_turns(GRID ? turns : -turns, &sn, &co);
         if (GRID) {
@@ -993,7 +994,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         const double l = double(min(p, N - 1) - half) * P.dl;   // bins outside the image are not used
         const double r2 = l * l + m * m;
         const double nm1 = -r2 / (1.0 + sqrt(1.0 - r2));     // n - 1
-        z[k] = nm1 / P.nscale + P.z0;                         // (n - n0) / n_scale
+        z[k] = nm1 / P.nscale + P.zshift;                     // (n - n0) / n_scale
         acc[k] = R(0);
     }
     for (int t = 0; t < P.pln; ++t) {
@@ -1050,7 +1051,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         const double l = double(min(p, N - 1) - half) * P.dl;   // keeps z finite on padding bins
         const double r2 = l * l + m * m;
         const double nm1 = -r2 / (1.0 + sqrt(1.0 - r2));
-        z[k] = nm1 / P.nscale + P.z0;
+        z[k] = nm1 / P.nscale + P.zshift;
     }
     for (int t = 0; t < P.pln; ++t) {
         const double tl = double(t + P.pl0 + P.t_lo);
@@ -1175,7 +1176,7 @@ __global__ void k_corr_map(const double* __restrict__ hx, const double* __restri
     if (i >= N) return;
     const double l = double(i - half) * P.dl, m = double(jrow - half) * P.dl;
     const double r2 = l * l + m * m;
-    const double z = (-r2 / (1.0 + sqrt(1.0 - r2))) / P.nscale + P.z0;
+    const double z = (-r2 / (1.0 + sqrt(1.0 - r2))) / P.nscale + P.zshift;
     const int W = P.W;
     double step_s, step_c;
     sincospi(2.0 * z, &step_s, &step_c);                         // exp(i 2 pi z)

@@ -142,7 +142,7 @@ DevParams dev_params(const wsg_plan* p) {
     P.pln = p->pp.n_layers();
     P.umul = p->pp.l_max / p->pp.x0;
     P.nscale = p->pp.n_scale;
-    P.z0 = p->pp.x0;
+    P.zshift = p->pp.z_shift;
     P.wmax = p->pp.wmax;
     P.dl = p->pp.L / p->pp.N;
     return P;
@@ -458,10 +458,10 @@ int wsg_stage_times(double* ms, int* launches, int n) {
     return WSG_NSTAGES;
 }
 
-int wsg_plan_params(int N, double L, int W, double x0, double wmax, int* Nprime, int* t_lo, int* t_hi,
-                    double* n0, double* n_scale) {
+int wsg_plan_params(int N, double L, int W, double x0, double wmax, int z_offset, int* Nprime, int* t_lo,
+                    int* t_hi, double* n0, double* n_scale) {
     PlanParams pp;
-    std::string e = make_plan_params(N, L, W, x0, wmax, &pp);
+    std::string e = make_plan_params(N, L, W, x0, wmax, &pp, z_offset != 0);
     if (!e.empty()) return fail(WSG_EINVAL, e);
     if (Nprime) *Nprime = pp.Nprime;
     if (t_lo) *t_lo = pp.t_lo;
@@ -493,10 +493,14 @@ int wsg_design_eval(int W, double x0, int n_nu, const double* nu, double* c_out,
 }
 
 wsg_plan* grid_create(int N, double L, int W, double x0, double wmax) {
+    return grid_create_variant(N, L, W, x0, wmax, 1);
+}
+
+wsg_plan* grid_create_variant(int N, double L, int W, double x0, double wmax, int z_offset) {
     wsg_plan* p = nullptr;
     try {
         PlanParams pp;
-        std::string e = make_plan_params(N, L, W, x0, wmax, &pp);
+        std::string e = make_plan_params(N, L, W, x0, wmax, &pp, z_offset != 0);
         if (!e.empty()) {
             fail(WSG_EINVAL, e);
             return nullptr;

@@ -25,6 +25,8 @@ _c_int_p = ctypes.POINTER(ctypes.c_int)
 
 _SIGNATURES = {
     "grid_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
+    "grid_create_variant": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_int]),
     "grid_destroy": (None, [ctypes.c_void_p]),
     "grid_plan_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, _c_int_p, _c_int_p, _c_double_p, _c_double_p,
                                       _c_double_p]),
@@ -43,7 +45,8 @@ _SIGNATURES = {
     "wsg_stage_timing": (None, [ctypes.c_int]),
     "wsg_stage_times": (ctypes.c_int, [_c_double_p, _c_int_p, ctypes.c_int]),
     "wsg_plan_params": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                                       ctypes.c_double, _c_int_p, _c_int_p, _c_int_p, _c_double_p, _c_double_p]),
+                                       ctypes.c_double, ctypes.c_int, _c_int_p, _c_int_p, _c_int_p, _c_double_p,
+                                       _c_double_p]),
 }
 
 
@@ -81,6 +84,13 @@ def grid_create(N: int, L: float, W: int, x0: float, wmax: float) -> int:
     p = lib().grid_create(N, L, W, x0, wmax)
     if not p:
         raise RuntimeError(f"grid_create failed: {lib().grid_last_error().decode()}")
+    return p
+
+
+def grid_create_variant(N: int, L: float, W: int, x0: float, wmax: float, z_offset: bool) -> int:
+    p = lib().grid_create_variant(N, L, W, x0, wmax, 1 if z_offset else 0)
+    if not p:
+        raise RuntimeError(f"grid_create_variant failed: {lib().grid_last_error().decode()}")
     return p
 
 
@@ -145,10 +155,10 @@ def wsg_design_eval(W: int, x0: float, nu, x):
     return c, h, E.value
 
 
-def wsg_plan_params(N: int, L: float, W: int, x0: float, wmax: float) -> dict:
+def wsg_plan_params(N: int, L: float, W: int, x0: float, wmax: float, z_offset: bool = True) -> dict:
     Np, tlo, thi = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     n0, ns = ctypes.c_double(), ctypes.c_double()
-    _err(lib().wsg_plan_params(N, L, W, x0, wmax, Np, tlo, thi, n0, ns), "wsg_plan_params")
+    _err(lib().wsg_plan_params(N, L, W, x0, wmax, 1 if z_offset else 0, Np, tlo, thi, n0, ns), "wsg_plan_params")
     return dict(Nprime=Np.value, t_lo=tlo.value, t_hi=thi.value, n0=n0.value, n_scale=ns.value)
 
 
@@ -181,17 +191,19 @@ class Plan:
 
     max_workspace_bytes caps the workspace each precision allocates: below
     grid_workspace_bytes the library takes the w-layers in passes (at least
-    grid_workspace_bytes_min is allocated).
+    grid_workspace_bytes_min is allocated).  z_offset=False selects the
+    variant without z offset (grid_create_variant).
     """
 
     def __init__(self, N: int, L: float, W: int, x0: float, wmax: float, device=None,
-                 max_workspace_bytes: int | None = None):
+                 max_workspace_bytes: int | None = None, z_offset: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("wsgrid needs a HIP device")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
         with torch.cuda.device(self.device):
-            self._p = grid_create(N, L, W, x0, wmax)
+            self._p = grid_create(N, L, W, x0, wmax) if z_offset else \
+                grid_create_variant(N, L, W, x0, wmax, False)
         self.N, self.L, self.W, self.x0, self.wmax = N, L, W, x0, wmax
         self.max_workspace_bytes = max_workspace_bytes
         self.info = grid_plan_info(self._p)

@@ -22,11 +22,12 @@ def test_exports_every_declared_function():
         assert hasattr(wg.lib(), n), n
 
 
+@pytest.mark.parametrize("z_offset", [True, False])
 @pytest.mark.parametrize("args", [(256, 0.2, 7, 0.25, 300.0), (2048, 0.4, 7, 0.25, 511.3),
                                   (2048, 0.4, 4, 0.5, 511.3), (64, 0.3, 5, 0.2, 10.0)])
-def test_planner_matches_oracle(args):
-    got = wg.wsg_plan_params(*args)
-    p = make_plan(*args)
+def test_planner_matches_oracle(args, z_offset):
+    got = wg.wsg_plan_params(*args, z_offset=z_offset)
+    p = make_plan(*args, z_offset=z_offset)
     assert got["Nprime"] == p.Nprime and got["t_lo"] == p.t_lo and got["t_hi"] == p.t_hi
     assert got["n0"] == p.n0 and got["n_scale"] == p.n_scale
 

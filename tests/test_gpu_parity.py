@@ -269,3 +269,24 @@ def test_workspace_below_minimum_is_rejected():
     with pytest.raises(RuntimeError, match="workspace too small"):
         wg.grid_visibilities(plan._p, wg.WSG_F32, M, uvw.data_ptr(), vis.data_ptr(), out.data_ptr(),
                              ws.data_ptr(), ws.numel(), torch.cuda.current_stream(DEV).cuda_stream)
+
+
+@pytest.mark.parametrize("case", [(64, 0.3, 7, 0.25, 100.0, 1000, 0.9), (128, 0.5, 5, 0.25, 250.0, 3000, 0.95)],
+                         ids=["N64W7", "N128W5"])
+def test_no_offset_variant(case):
+    """The planner variant without z offset (Sec. 5.3, eq. n_params_no_offset):
+    n0 = 1, z in [-z0, 0], about twice the layers; against the oracle's variant."""
+    N, L, W, x0, wmax, M, frac = case
+    uvw, vis, img = _case(*case, seed=71)
+    op, lm = make_plan(N, L, W, x0, wmax, z_offset=False), least_misfit(W, x0)
+    ref_g = wstack.grid(op, lm, uvw, vis)
+    ref_d = wstack.degrid(op, lm, uvw, img)
+    plan = wg.Plan(N, L, W, x0, wmax, device=DEV, z_offset=False)
+    assert plan.info["n0"] == 1.0 and plan.info["n_scale"] == op.n_scale
+    assert plan.info["n_layers"] == op.n_layers > make_plan(N, L, W, x0, wmax).n_layers
+    for prec, tol in ((64, 1e-10), (32, 1e-6)):
+        g = gpu_grid(plan, uvw, vis, prec)
+        d = gpu_degrid(plan, uvw, img, prec)
+        assert rel(g, ref_g) <= tol, (prec, "grid", rel(g, ref_g))
+        assert rel(d, ref_d) <= tol, (prec, "degrid", rel(d, ref_d))
+    plan.close()
