@@ -316,6 +316,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=60000)
     ap.add_argument("--copy-gb", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GB (counter calibration)")
+    ap.add_argument("--no-z-offset", action="store_true",
+                    help="widefield: the planner variant without z offset (Sec. 5.3; about twice the layers)")
     ap.add_argument("--workload", choices=("widefield", "imaging"), default="widefield",
                     help="imaging: one differentiable-imaging gradient step per step (4096^2, 50M visibilities)")
     ap.add_argument("--max-workspace-gb", type=float, default=96.0, help="imaging: workspace cap (layer passes)")
@@ -345,7 +347,7 @@ def main() -> int:
     w = inputs.workload("widefield", n_dumps=args.dumps, vis_dtype=np.complex64)
     N, L, W, x0, wmax = w["N"], w["L"], w["W"], w["x0"], w["wmax"]
     M = w["uvw"].shape[0]
-    plan = wsgrid.Plan(N, L, W, x0, wmax, device=dev)
+    plan = wsgrid.Plan(N, L, W, x0, wmax, device=dev, z_offset=not args.no_z_offset)
     info = plan.info
     Np, nl = info["Nprime"], info["n_layers"]
     log(f"M={M} N={N} N'={Np} layers={nl} E={info['E']:.3e}")
@@ -414,8 +416,10 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": (f"wide-field single channel: {N}x{N} image, L={L}, W={W}, x0={x0}, {M} "
                                 f"visibilities (64 antennas in a 5 km disc, +-1 h tracks, dec -30, 1.4 GHz, "
-                                f"uvw scaled to a Nyquist-sampled image), {nl} w-layers, N'={Np}"),
-                   "N": N, "L": L, "W": W, "x0": x0, "visibilities": M, "w_layers": nl, "fft_size": Np},
+                                f"uvw scaled to a Nyquist-sampled image), {nl} w-layers, N'={Np}"
+                                + (", planner without z offset" if args.no_z_offset else "")),
+                   "N": N, "L": L, "W": W, "x0": x0, "visibilities": M, "w_layers": nl, "fft_size": Np,
+                   "z_offset": not args.no_z_offset},
         "roofline": roofline,
         "whole_step_alg_GBps": total_alg / (ms32 * 1e-3) / 1e9,
         "fp64": fp64,
