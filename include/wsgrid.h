@@ -140,6 +140,42 @@ int degrid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double*
                         const void* image, void* vis, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Batched channels: nch (1..64) channels on one plan, each with its own
+ * visibilities (uvw in wavelengths at its own frequency, |w| <= wmax), gridded
+ * to or degridded from its own map in one call whose binning, tile and FFT
+ * stages are each one launch over all channels (Algorithms 5 and 6 applied per
+ * channel; channels are independent).  Internally channel c's w-layers follow
+ * channel c - 1's on one layer axis, so the workspace holds the channels'
+ * layers together and the layer passes of grid_workspace_bytes_min run across
+ * channel boundaries.
+ *   M     [nch] visibility counts (host memory), any may be 0;
+ *   uvw   [sum M][3] float64 device, the channels' visibilities one after the
+ *         other (channel 0 first); vis [sum M] complex (prec) device, same order;
+ *   dirty [nch][N][N] real (prec) device, overwritten (grid);
+ *   image [nch][N][N] real (prec) device (degrid); vis overwritten (degrid);
+ *   ws    device workspace of ws_bytes >= grid_workspace_bytes_batch(plan,
+ *         prec, nch, sum M, 1); with grid_workspace_bytes_batch(..., 0) every
+ *         layer of every channel is held at once.
+ * The result of channel c equals grid_visibilities / degrid_visibilities on
+ * channel c alone (degrid: bit for bit; grid: up to the rounding order of the
+ * sum over layer passes).  Errors as for the single-channel calls, plus
+ * WSG_EINVAL for nch outside [1, 64], a sum of M of 2^31 or more, or more than
+ * 2^25 tiles over the channels.
+ */
+int grid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int64_t* M, const double* uvw,
+                            const void* vis, void* dirty, void* ws, size_t ws_bytes, void* stream);
+int degrid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int64_t* M, const double* uvw,
+                              const void* image, void* vis, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Workspace (bytes) of a batched call with nch channels and M visibilities in
+ * all: min_passes = 0 holds every layer of every channel at once, 1 gives the
+ * smallest workspace the call accepts (one tile layer of 16 w-layers per
+ * pass).  0 on a bad argument.
+ */
+size_t grid_workspace_bytes_batch(const wsg_plan* plan, int prec, int nch, int64_t M, int min_passes);
+
+/*
  * Number of visibilities skipped (|w| > wmax or non-finite) by the last call
  * that used workspace `ws`.  Waits for `stream`.  Returns < 0 on error.
  */

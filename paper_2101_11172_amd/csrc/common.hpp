@@ -75,9 +75,14 @@ struct Rec {
 // Scalars every kernel needs, passed by value.
 struct DevParams {
     int N, Np, W, n_layers, t_lo;
-    int nbr, nbs, nbt;      // bins (= tiles) along r (u), s (v), t (w)
-    // layer pass: layers [pl0, pl0 + pln) (counted from t_lo; pl0 a multiple of
-    // kTileT) sit in the stack and FFT buffers, local layer index t - pl0
+    int nbr, nbs, nbt;      // bins (= tiles) along r (u), s (v), t (w) of one channel
+    // Channels of a batched call: channel c's layers are the virtual layers
+    // [c chl, c chl + n_layers) with chl = nbt kTileT (its tile layers follow
+    // the previous channel's); virtual layers beyond n_layers in a channel are
+    // padding that nothing reads or writes.  One channel: virtual = plain.
+    int nch;
+    // layer pass: virtual layers [pl0, pl0 + pln) (pl0 a multiple of kTileT)
+    // sit in the stack and FFT buffers, local layer index t - pl0
     int pl0, pln;
     double umul;            // l_max / x0: u -> u'
     double nscale;          // w -> w'

@@ -38,7 +38,8 @@ __device__ __forceinline__ bool axis_support(double xi, int W, double& nu, long 
     return true;
 }
 
-__device__ __forceinline__ bool vis_coords(const double* __restrict__ uvw, long long k,
+// ch: the visibility's channel (virtual layer offset ch nbt kTileT)
+__device__ __forceinline__ bool vis_coords(const double* __restrict__ uvw, long long k, int ch,
                                            const DevParams& P, VisCoords& c) {
     double u = uvw[3 * k], v = uvw[3 * k + 1], w = uvw[3 * k + 2];
     if (!isfinite(u) || !isfinite(v) || !isfinite(w)) return false;
@@ -61,7 +62,7 @@ __device__ __forceinline__ bool vis_coords(const double* __restrict__ uvw, long 
     c.rv = int(fv & mask);
     long long it = ft - P.t_lo;
     if (it < 0 || it > P.n_layers - P.W) return false;
-    c.rt = int(it);
+    c.rt = int(it) + ch * P.nbt * kTileT;
     c.w = w;
     return true;
 }
@@ -89,6 +90,26 @@ struct AggTable {
     uint32_t skipped;
 };
 
+// Binning blocks of a batched call: block b belongs to channel c when
+// cblk[c] <= b < cblk[c + 1]; channel c's visibilities are [coff[c], coff[c + 1])
+// of the concatenated arrays, kAggChunk of them per block (one channel per
+// block, so the lookup is wave-uniform).
+struct ChunkRange {
+    long long k0, k1;
+    int ch;
+};
+__device__ __forceinline__ ChunkRange chunk_of_block(const long long* __restrict__ coff,
+                                                     const int* __restrict__ cblk, int nch) {
+    const int b = blockIdx.x;
+    int c = 0;
+    while (c + 1 < nch && cblk[c + 1] <= b) ++c;
+    ChunkRange r;
+    r.ch = c;
+    r.k0 = coff[c] + (long long)(b - cblk[c]) * kAggChunk;
+    r.k1 = min(coff[c + 1], r.k0 + kAggChunk);
+    return r;
+}
+
 __device__ __forceinline__ void agg_init(AggTable& T) {
     for (int i = threadIdx.x; i < kAggSlots; i += blockDim.x) {
         T.key[i] = -1;
@@ -112,19 +133,21 @@ __device__ __forceinline__ int agg_slot(AggTable& T, int key) {
     return -1;
 }
 
-__global__ void __launch_bounds__(kAggThreads) k_bin_count(const double* __restrict__ uvw, long long M, DevParams P,
+__global__ void __launch_bounds__(kAggThreads) k_bin_count(const double* __restrict__ uvw,
+                                                           const long long* __restrict__ coff,
+                                                           const int* __restrict__ cblk, DevParams P,
                                                            uint32_t* __restrict__ count,
                                                            uint32_t* __restrict__ skipped) {
     __shared__ AggTable T;
     agg_init(T);
     __syncthreads();
-    const long long k0 = (long long)blockIdx.x * kAggChunk;
+    const ChunkRange cr = chunk_of_block(coff, cblk, P.nch);
     uint32_t my_skipped = 0;
     for (int i = 0; i < kAggPer; ++i) {
-        const long long k = k0 + (long long)i * kAggThreads + threadIdx.x;
-        if (k >= M) break;
+        const long long k = cr.k0 + (long long)i * kAggThreads + threadIdx.x;
+        if (k >= cr.k1) break;
         VisCoords c;
-        if (!vis_coords(uvw, k, P, c)) {
+        if (!vis_coords(uvw, k, cr.ch, P, c)) {
             ++my_skipped;
             continue;
         }
@@ -183,22 +206,22 @@ __global__ void k_scan_local(const uint32_t* __restrict__ in, uint32_t* __restri
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
-// single block of 1024 threads, nb <= 4096
+// single block of 1024 threads; each thread scans ceil(nb / 1024) consecutive sums
 __global__ void k_scan_sums(uint32_t* __restrict__ block_sums, int nb, uint32_t* __restrict__ grand) {
     __shared__ uint32_t sh[16];
-    const int base = threadIdx.x * 4;
-    uint32_t v[4], s = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        v[i] = (base + i < nb) ? block_sums[base + i] : 0u;
-        s += v[i];
-    }
+    const int per = (nb + 1023) / 1024;
+    const int base = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int i = 0; i < per; ++i)
+        if (base + i < nb) s += block_sums[base + i];
     uint32_t total;
     uint32_t off = block_exclusive_scan(s, sh, total);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (base + i < nb) block_sums[base + i] = off;
-        off += v[i];
+    for (int i = 0; i < per; ++i) {
+        if (base + i < nb) {
+            const uint32_t v = block_sums[base + i];
+            block_sums[base + i] = off;
+            off += v;
+        }
     }
     if (threadIdx.x == 0) *grand = total;
 }
@@ -216,13 +239,16 @@ __global__ void k_scan_add(uint32_t* __restrict__ out, int n, const uint32_t* __
 // V conjugated for a folded visibility.  degrid: v = exp(-i 2 pi w (n0 - 1)).
 template <typename R, bool GRID>
 __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __restrict__ uvw,
-                                                             const cpx<R>* __restrict__ vis, long long M, DevParams P,
+                                                             const cpx<R>* __restrict__ vis,
+                                                             const long long* __restrict__ coff,
+                                                             const int* __restrict__ cblk, DevParams P,
                                                              const uint32_t* __restrict__ start,
                                                              uint32_t* __restrict__ cursor, Rec<R>* __restrict__ rec) {
     __shared__ AggTable T;
     agg_init(T);
     __syncthreads();
-    const long long k0 = (long long)blockIdx.x * kAggChunk;
+    const ChunkRange cr = chunk_of_block(coff, cblk, P.nch);
+    const long long k0 = cr.k0;
     // pass 1: rank of each visibility among this block's visibilities of its bin
     uint32_t tag[kAggPer];             // slot << 16 | rank; 0xffffffff: direct update
 #pragma unroll
@@ -230,7 +256,7 @@ __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __res
         tag[i] = 0xffffffffu;
         const long long k = k0 + (long long)i * kAggThreads + threadIdx.x;
         VisCoords c;
-        if (k < M && vis_coords(uvw, k, P, c)) {
+        if (k < cr.k1 && vis_coords(uvw, k, cr.ch, P, c)) {
             const int sl = agg_slot(T, bin_of(c, P));
             if (sl >= 0) tag[i] = (uint32_t(sl) << 16) | atomicAdd(&T.cnt[sl], 1u);
         }
@@ -245,7 +271,7 @@ __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __res
     for (int i = 0; i < kAggPer; ++i) {
         const long long k = k0 + (long long)i * kAggThreads + threadIdx.x;
         VisCoords c;
-        if (!(k < M && vis_coords(uvw, k, P, c))) continue;
+        if (!(k < cr.k1 && vis_coords(uvw, k, cr.ch, P, c))) continue;
         const int b = bin_of(c, P);
         const uint32_t off = tag[i] != 0xffffffffu ? T.base[tag[i] >> 16] + (tag[i] & 0xffffu)
                                                    : atomicAdd(&cursor[b], 1u);
@@ -362,13 +388,13 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
 __global__ void k_tile_occupancy(const uint32_t* __restrict__ start, const uint32_t* __restrict__ cls, DevParams P,
                                  uint8_t* __restrict__ occ, uint8_t* __restrict__ rows) {
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nt = P.nbt * P.nbs * P.nbr;
+    const int nt = P.nch * P.nbt * P.nbs * P.nbr;
     if (tile >= nt) return;
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     bool any = false;
     for (int nb = 0; nb < 8 && !any; ++nb) {
         const int it = (nb >> 2) & 1, is = (nb >> 1) & 1, ir = nb & 1;
-        if (bt - it < 0) continue;
+        if (bt % P.nbt - it < 0) continue;      // not across a channel start
         const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
         const uint32_t b0 = start[bin], b1 = start[bin + 1];
         if (b1 == b0) continue;
@@ -422,7 +448,7 @@ __device__ __forceinline__ void tile_segments(const uint32_t* __restrict__ start
     const int it = (nb >> 2) & 1, is = (nb >> 1) & 1, ir = nb & 1;
     uint32_t lo = 0, hi = 0;
     bool need = false;
-    if (bt - it >= 0) {
+    if (bt % P.nbt - it >= 0) {      // not across a channel start
         const int bin = ((bt - it) * P.nbs + (bs - is + P.nbs) % P.nbs) * P.nbr + (br - ir + P.nbr) % P.nbr;
         const uint32_t b0 = start[bin], b1 = start[bin + 1];
         if (b1 > b0) {
@@ -573,7 +599,7 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     if (!occ[tile]) return;     // no visibility reaches it: left unwritten, read as zero
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
-    const int nt_valid = min(kTileT, P.n_layers - t0);
+    const int nt_valid = min(kTileT, P.n_layers - t0 % (P.nbt * kTileT));   // layers of its channel
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
 
@@ -776,7 +802,7 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     const int tile = tile_of_block(P);
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
-    const int nt_valid = min(kTileT, P.n_layers - t0);
+    const int nt_valid = min(kTileT, P.n_layers - t0 % (P.nbt * kTileT));   // layers of its channel
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
 
@@ -922,7 +948,7 @@ struct FftCfg {
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_grid_fft_a(const cpx<R>* __restrict__ stack, const uint8_t* __restrict__ occ, cpx<R>* __restrict__ inter,
-                 const cpx<R>* __restrict__ tw, int N, int n_layers, int nbr, int t_base) {
+                 const cpx<R>* __restrict__ tw, int N, int n_layers, int chl, int nbr, int t_base) {
     using C = FftCfg<R, LOGN>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size, NG = kTileR / NL;
     static_assert(kTileR % NL == 0, "a row of tiles is a whole number of line groups");
@@ -930,6 +956,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     const int rows = Np / kTileR;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int t = lb / rows, rt = lb % rows;
+    if (chl > 0 && (t + t_base) % chl >= n_layers) return;     // padding layer of a channel (block-uniform)
     const int line = threadIdx.x / T, j = threadIdx.x % T;
     cpx<R>* lbuf = buf + line * LP;
     // tile (t / 16, s / 16, rt) holds s = j + T k
@@ -972,7 +999,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
     k_grid_fft_b(const cpx<R>* __restrict__ inter, const cpx<R>* __restrict__ tw, const R* __restrict__ corr,
-                 R* __restrict__ dirty, DevParams P) {
+                 R* __restrict__ dirty, DevParams P, int seg0, int tloc0, int accumulate) {
     using C = FftCfg<R, LOGN>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLr, LP = LinePad<Np>::size;
     __shared__ cpx<R> buf[NL * LP];
@@ -998,12 +1025,12 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         acc[k] = R(0);
     }
     for (int t = 0; t < P.pln; ++t) {
-        const cpx<R>* src = inter + ((size_t)t * N + qq) * Np;
+        const cpx<R>* src = inter + ((size_t)(seg0 + t) * N + qq) * Np;
         cpx<R> v[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) v[k] = src[j + T * k];
         fft_line<R, LOGN, +1>(v, lbuf, tw, j);
-        const double tl = double(t + P.pl0 + P.t_lo);
+        const double tl = double(tloc0 + t + P.t_lo);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (pix[k] >= 0) {
@@ -1014,13 +1041,13 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         }
     }
     if (!row_ok) return;
-    // the first layer pass writes the map, later ones add to it
+    // the channel's first layer segment writes the map, later ones add to it
 #pragma unroll
     for (int k = 0; k < 16; ++k)
         if (pix[k] >= 0) {
             const size_t o = (size_t)q * N + pix[k];
             const R d = acc[k] * corr[o];
-            dirty[o] = P.pl0 > 0 ? dirty[o] + d : d;
+            dirty[o] = accumulate ? dirty[o] + d : d;
         }
 }
 
@@ -1029,7 +1056,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
     k_degrid_fft_b(const R* __restrict__ image, const R* __restrict__ corr, const cpx<R>* __restrict__ tw,
-                   cpx<R>* __restrict__ inter, DevParams P) {
+                   cpx<R>* __restrict__ inter, DevParams P, int seg0, int tloc0) {
     using C = FftCfg<R, LOGN>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLr, LP = LinePad<Np>::size;
     __shared__ cpx<R> buf[NL * LP];
@@ -1054,7 +1081,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         z[k] = nm1 / P.nscale + P.zshift;
     }
     for (int t = 0; t < P.pln; ++t) {
-        const double tl = double(t + P.pl0 + P.t_lo);
+        const double tl = double(tloc0 + t + P.t_lo);
         cpx<R> v[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -1064,7 +1091,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         }
         fft_line<R, LOGN, -1>(v, lbuf, tw, j);
         if (row_ok) {
-            cpx<R>* dst = inter + ((size_t)t * N + q) * Np;
+            cpx<R>* dst = inter + ((size_t)(seg0 + t) * N + q) * Np;
 #pragma unroll
             for (int k = 0; k < 16; ++k) dst[j + T * k] = v[k];
         }
@@ -1080,7 +1107,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_degrid_fft_a(const cpx<R>* __restrict__ inter, const uint8_t* __restrict__ occ, const cpx<R>* __restrict__ tw,
-                   cpx<R>* __restrict__ stack, int N, int n_layers, int nbr, int t_base) {
+                   cpx<R>* __restrict__ stack, int N, int n_layers, int chl, int nbr, int t_base) {
     using C = FftCfg<R, LOGN>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size, NG = kTileR / NL;
     static_assert(kTileR % NL == 0, "a row of tiles is a whole number of line groups");
@@ -1088,6 +1115,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     const int rows = Np / kTileR;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int t = lb / rows, rt = lb % rows;
+    if (chl > 0 && (t + t_base) % chl >= n_layers) return;     // padding layer of a channel (block-uniform)
     const int line = threadIdx.x / T, j = threadIdx.x % T;
     cpx<R>* lbuf = buf + line * LP;
     const uint8_t* orow = occ + (size_t)((t + t_base) / kTileT) * (Np / kTileS) * nbr + rt;
@@ -1134,12 +1162,13 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
 template <typename R, int THREADS, bool R_IN>
 __global__ void __launch_bounds__(THREADS) k_transpose(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
                                                        int A, int B, const uint8_t* __restrict__ rows, int nbr,
-                                                       int t_base) {
+                                                       int t_base, int chl, int n_layers) {
     __shared__ cpx<R> tile[64][65];
     __shared__ uint8_t live[4];
     const int ta_n = (A + 63) / 64, tb_n = (B + 63) / 64;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int t = lb / (ta_n * tb_n), rem = lb % (ta_n * tb_n);
+    if (chl > 0 && (t + t_base) % chl >= n_layers) return;     // padding layer of a channel (block-uniform)
     const int a0 = (rem / tb_n) * 64, b0 = (rem % tb_n) * 64;
     const int r0 = R_IN ? a0 : b0;
     if (threadIdx.x < 4)

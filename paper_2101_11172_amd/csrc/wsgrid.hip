@@ -43,7 +43,7 @@ int fail(int code, const std::string& msg) {
         if (e_ != hipSuccess) return fail(WSG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int kMaxBins = 4096 * 1024;   // limit of the three-kernel scan
+constexpr int kMaxBins = 1 << 25;   // bins over all channels (the bin tables take ~50 bytes per bin)
 
 // per-thread stage timing (wsg_stage_timing / wsg_stage_times)
 struct StageEvent {
@@ -92,21 +92,35 @@ struct wsg_plan {
 namespace {
 
 struct Layout {
-    size_t stack, inter, inter2, rec, rec2, part, count, start, cursor, bsums, cls, occ, rows, skipped, total;
-    int nbins, nscan;
-    int pass_layers;   // w-layers held in the stack and FFT buffers at a time (a multiple of kTileT, or all)
+    size_t stack, inter, inter2, rec, rec2, part, count, start, cursor, bsums, cls, occ, rows, chan, skipped, total;
+    int nch, nbins, nscan;
+    int last_layer;    // end of the last channel's layers on the virtual layer axis
+    int pass_layers;   // virtual layers held in the stack and FFT buffers at a time (a multiple of kTileT, or all)
+};
+
+constexpr int kMaxChannels = 64;
+
+// Channel table of a batched call, copied to the workspace by one tiny kernel:
+// visibility offsets and first binning block of each channel.
+struct ChanArgs {
+    long long off[kMaxChannels + 1];
+    int blk[kMaxChannels + 1];
 };
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+size_t al2m(size_t x) { return (x + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1); }
 
-// Workspace for passes of `tiles_per_pass` tile layers (kTileT w-layers each).
-Layout layout_of(const wsg_plan* p, int prec, int64_t M, int tiles_per_pass) {
+// Workspace for nch channels (M visibilities in all) taken in passes of
+// `tiles_per_pass` tile layers (kTileT virtual layers each).
+Layout layout_of(const wsg_plan* p, int prec, int64_t M, int tiles_per_pass, int nch = 1) {
     Layout L{};
     const size_t cs = prec == WSG_F32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
     const size_t rs = prec == WSG_F32 ? sizeof(Rec<float>) : sizeof(Rec<double>);
-    L.pass_layers = std::min(p->pp.n_layers(), std::max(1, std::min(tiles_per_pass, p->nbt)) * kTileT);
+    L.nch = nch;
+    L.last_layer = (nch - 1) * p->nbt * kTileT + p->pp.n_layers();
+    L.pass_layers = std::min(L.last_layer, std::max(1, std::min(tiles_per_pass, nch * p->nbt)) * kTileT);
     const size_t Np = size_t(p->pp.Nprime), N = size_t(p->pp.N), nl = size_t(L.pass_layers);
-    L.nbins = p->nbins();
+    L.nbins = nch * p->nbins();
     L.nscan = (L.nbins + 1023) / 1024;
     // the skipped counter sits at offset 0 whatever M and the precision
     size_t off = 0;
@@ -117,10 +131,14 @@ Layout layout_of(const wsg_plan* p, int prec, int64_t M, int tiles_per_pass) {
     L.bsums = off;   off += al256(size_t(L.nscan) * 4);
     L.cls = off;     off += al256(size_t(L.nbins) * 8 * 4);
     L.occ = off;     off += al256(size_t(L.nbins));
-    L.rows = off;    off += al256(size_t(p->nbt) * p->nbr);
-    L.stack = off;   off += al256(nl * Np * Np * cs);
-    L.inter = off;   off += al256(nl * N * Np * cs);
-    L.inter2 = off;  off += al256(nl * N * Np * cs);   // the transposed intermediate
+    L.rows = off;    off += al256(size_t(nch) * p->nbt * p->nbr);
+    L.chan = off;    off += al256(sizeof(long long) * (kMaxChannels + 1)) + al256(sizeof(int) * (kMaxChannels + 1));
+    // the large buffers start on 2 MiB boundaries (their power-of-two line
+    // strides then meet the memory channels the same way whatever precedes them)
+    off = al2m(off);
+    L.stack = off;   off += al2m(nl * Np * Np * cs);
+    L.inter = off;   off += al2m(nl * N * Np * cs);
+    L.inter2 = off;  off += al2m(nl * N * Np * cs);   // the transposed intermediate
     L.rec = off;     off += al256(size_t(M) * rs);
     L.rec2 = off;    off += al256(size_t(M) * rs);
     L.part = off;    off += al256(size_t(8) * size_t(M) * cs);   // degrid: per-tile parts
@@ -138,6 +156,7 @@ DevParams dev_params(const wsg_plan* p) {
     P.nbr = p->nbr;
     P.nbs = p->nbs;
     P.nbt = p->nbt;
+    P.nch = 1;
     P.pl0 = 0;
     P.pln = p->pp.n_layers();
     P.umul = p->pp.l_max / p->pp.x0;
@@ -198,39 +217,61 @@ void transpose(const DevParams& P, const cpx<R>* in, cpx<R>* out, int A, int B, 
                hipStream_t s) {
     constexpr int TH = 512;
     const unsigned blocks = unsigned(P.pln) * unsigned((A + 63) / 64) * unsigned((B + 63) / 64);
+    const int chl = P.nch > 1 ? P.nbt * kTileT : 0;     // 0: one channel, no padding layers to skip
     if (r_in)
         hipLaunchKernelGGL((k_transpose<R, TH, true>), dim3(blocks), dim3(TH), 0, s, in, out, A, B, rows, P.nbr,
-                           P.pl0);
+                           P.pl0, chl, P.n_layers);
     else
         hipLaunchKernelGGL((k_transpose<R, TH, false>), dim3(blocks), dim3(TH), 0, s, in, out, A, B, rows, P.nbr,
-                           P.pl0);
+                           P.pl0, chl, P.n_layers);
 }
 
+// One layer pass of the FFT stages.  Pass B (along u / p, with the w-screen)
+// runs once per channel segment of the pass: the virtual layers of channel c
+// in the pass, whose map is dirty + c N^2 (grid, written by the channel's first
+// segment and added to by later ones) or image + c N^2 (degrid).
 template <typename R, int LOGN>
 void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, const uint8_t* rows, cpx<R>* stack, cpx<R>* inter,
-                  cpx<R>* inter2,
-                  const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
+                  cpx<R>* inter2, const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
     using C = FftCfg<R, LOGN>;
     const unsigned grid_a = unsigned(P.pln) * unsigned(C::N / kTileR);
     const unsigned grid_b = unsigned((P.N + C::kNLr - 1) / C::kNLr);
+    const int chl = P.nbt * kTileT;
+    const size_t map = size_t(P.N) * size_t(P.N);
+    auto segments = [&](auto&& fn) {
+        for (int c = P.pl0 / chl; c < P.nch && c * chl < P.pl0 + P.pln; ++c) {
+            const int lo = std::max(P.pl0, c * chl), hi = std::min(P.pl0 + P.pln, c * chl + P.n_layers);
+            if (hi > lo) fn(c, lo, hi);
+        }
+    };
     if (grid) {
         {
             StageMark mark(s, 2);
             hipLaunchKernelGGL((k_grid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
-                               (const cpx<R>*)stack, occ, inter, tw, P.N, P.pln, P.nbr, P.pl0);
+                               (const cpx<R>*)stack, occ, inter, tw, P.N, P.n_layers, P.nch > 1 ? chl : 0, P.nbr,
+                               P.pl0);
         }
         {
             StageMark mark(s, 8);
             transpose<R>(P, inter, inter2, P.Np, P.N, true, rows, s);     // [t][r][q] -> [t][q][r]
         }
         StageMark mark(s, 3);
-        hipLaunchKernelGGL((k_grid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
-                           (const cpx<R>*)inter2, tw, corr, dirty, P);
+        segments([&](int c, int lo, int hi) {
+            DevParams Q = P;
+            Q.pln = hi - lo;
+            hipLaunchKernelGGL((k_grid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
+                               (const cpx<R>*)inter2, tw, corr, dirty + size_t(c) * map, Q, lo - P.pl0, lo - c * chl,
+                               lo > c * chl ? 1 : 0);
+        });
     } else {
         {
             StageMark mark(s, 5);
-            hipLaunchKernelGGL((k_degrid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s, image, corr,
-                               tw, inter, P);
+            segments([&](int c, int lo, int hi) {
+                DevParams Q = P;
+                Q.pln = hi - lo;
+                hipLaunchKernelGGL((k_degrid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
+                                   image + size_t(c) * map, corr, tw, inter, Q, lo - P.pl0, lo - c * chl);
+            });
         }
         {
             StageMark mark(s, 9);
@@ -238,7 +279,8 @@ void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, const uint8
         }
         StageMark mark(s, 6);
         hipLaunchKernelGGL((k_degrid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
-                           (const cpx<R>*)inter2, occ, tw, stack, P.N, P.pln, P.nbr, P.pl0);
+                           (const cpx<R>*)inter2, occ, tw, stack, P.N, P.n_layers, P.nch > 1 ? chl : 0, P.nbr,
+                           P.pl0);
     }
 }
 
@@ -255,21 +297,40 @@ void launch_fft(bool grid, int log2n, const DevParams& P, const uint8_t* occ, co
     }
 }
 
+__global__ void k_set_chan(ChanArgs ca, int nch, long long* __restrict__ coff, int* __restrict__ cblk) {
+    const int i = threadIdx.x;
+    if (i <= nch) {
+        coff[i] = ca.off[i];
+        cblk[i] = ca.blk[i];
+    }
+}
+
 // a: the input array, b: the output array; with M = 0 the visibility-sized
-// one of them may be null (nothing is read from or written to it).
-int check_call(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* a, bool a_empty_ok,
-               const void* b, bool b_empty_ok, void* ws, size_t ws_bytes, Layout* L) {
+// one of them may be null (nothing is read from or written to it).  Mc: the
+// nch channels' visibility counts (host); *M receives their sum.
+int check_call(const wsg_plan* plan, int prec, int nch, const int64_t* Mc, int64_t* M, const double* uvw,
+               const void* a, bool a_empty_ok, const void* b, bool b_empty_ok, void* ws, size_t ws_bytes,
+               Layout* L) {
     if (!plan) return fail(WSG_EINVAL, "null plan");
     if (prec != WSG_F32 && prec != WSG_F64) return fail(WSG_EINVAL, "prec must be WSG_F32 or WSG_F64");
-    if (M < 0 || M > 0x7fffffffLL) return fail(WSG_EINVAL, "M must be in [0, 2^31)");
-    if (M > 0 && !uvw) return fail(WSG_EINVAL, "null uvw pointer");
-    if (!a && (M > 0 || !a_empty_ok)) return fail(WSG_EINVAL, "null visibility/image pointer");
-    if (!b && (M > 0 || !b_empty_ok)) return fail(WSG_EINVAL, "null output pointer");
+    if (nch < 1 || nch > kMaxChannels) return fail(WSG_EINVAL, "channels must be in [1, 64]");
+    if (!Mc) return fail(WSG_EINVAL, "null visibility counts");
+    int64_t tot = 0;
+    for (int c = 0; c < nch; ++c) {
+        if (Mc[c] < 0 || Mc[c] > 0x7fffffffLL) return fail(WSG_EINVAL, "M must be in [0, 2^31)");
+        tot += Mc[c];
+    }
+    if (tot > 0x7fffffffLL) return fail(WSG_EINVAL, "total M must be below 2^31");
+    *M = tot;
+    if ((long long)nch * plan->nbins() > kMaxBins) return fail(WSG_EINVAL, "too many tiles over the channels");
+    if (tot > 0 && !uvw) return fail(WSG_EINVAL, "null uvw pointer");
+    if (!a && (tot > 0 || !a_empty_ok)) return fail(WSG_EINVAL, "null visibility/image pointer");
+    if (!b && (tot > 0 || !b_empty_ok)) return fail(WSG_EINVAL, "null output pointer");
     if (!ws) return fail(WSG_EINVAL, "null workspace");
     // as many tile layers per pass as the workspace holds
-    int tiles = plan->nbt;
-    *L = layout_of(plan, prec, M, tiles);
-    while (tiles > 1 && ws_bytes < L->total) *L = layout_of(plan, prec, M, --tiles);
+    int tiles = nch * plan->nbt;
+    *L = layout_of(plan, prec, tot, tiles, nch);
+    while (tiles > 1 && ws_bytes < L->total) *L = layout_of(plan, prec, tot, --tiles, nch);
     if (ws_bytes < L->total)
         return fail(WSG_EWORKSPACE, "workspace too small: need at least " + std::to_string(L->total) + " bytes");
     int dev = -1;
@@ -279,9 +340,10 @@ int check_call(const wsg_plan* plan, int prec, int64_t M, const double* uvw, con
 }
 
 template <typename R>
-int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const void* in, void* out, void* ws,
-        const Layout& L, hipStream_t s) {
-    const DevParams P = dev_params(plan);
+int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const double* uvw, const void* in, void* out,
+        void* ws, const Layout& L, hipStream_t s) {
+    DevParams P = dev_params(plan);
+    P.nch = L.nch;
     char* w = static_cast<char*>(ws);
     auto* stack = reinterpret_cast<cpx<R>*>(w + L.stack);
     auto* inter = reinterpret_cast<cpx<R>*>(w + L.inter);
@@ -295,48 +357,60 @@ int run(const wsg_plan* plan, bool grid, int64_t M, const double* uvw, const voi
     auto* cls = reinterpret_cast<uint32_t*>(w + L.cls);
     auto* occ = reinterpret_cast<uint8_t*>(w + L.occ);
     auto* rows = reinterpret_cast<uint8_t*>(w + L.rows);
+    auto* coff = reinterpret_cast<long long*>(w + L.chan);
+    auto* cblk = reinterpret_cast<int*>(w + L.chan + al256(sizeof(long long) * (kMaxChannels + 1)));
     auto* skipped = reinterpret_cast<uint32_t*>(w + L.skipped);
     const bool f64 = sizeof(R) == 8;
     const R* coef = f64 ? reinterpret_cast<const R*>(plan->poly64) : reinterpret_cast<const R*>(plan->poly32);
     const R* corr = f64 ? reinterpret_cast<const R*>(plan->corr64) : reinterpret_cast<const R*>(plan->corr32);
     const cpx<R>* tw = f64 ? reinterpret_cast<const cpx<R>*>(plan->tw64) : reinterpret_cast<const cpx<R>*>(plan->tw32);
 
+    // channel table: visibility offsets and binning blocks (one channel per block)
+    ChanArgs ca{};
+    for (int c = 0; c < L.nch; ++c) {
+        ca.off[c + 1] = ca.off[c] + Mc[c];
+        ca.blk[c + 1] = ca.blk[c] + int((Mc[c] + kAggChunk - 1) / kAggChunk);
+    }
+    const unsigned vblocks = unsigned(ca.blk[L.nch]);
     {
         StageMark mark(s, grid ? 0 : 4);
+        hipLaunchKernelGGL(k_set_chan, dim3(1), dim3(128), 0, s, ca, L.nch, coff, cblk);
         fill<uint32_t>(count, size_t(L.nbins), 0u, s);
         fill<uint32_t>(cursor, size_t(L.nbins), 0u, s);
         fill<uint32_t>(skipped, 1, 0u, s);
-        const unsigned vblocks = unsigned((M + kAggChunk - 1) / kAggChunk);
-        if (M > 0)
-            hipLaunchKernelGGL(k_bin_count, dim3(vblocks), dim3(kAggThreads), 0, s, uvw, (long long)M, P, count,
-                               skipped);
+        if (vblocks > 0)
+            hipLaunchKernelGGL(k_bin_count, dim3(vblocks), dim3(kAggThreads), 0, s, uvw, (const long long*)coff,
+                               (const int*)cblk, P, count, skipped);
         scan(count, start, bsums, L.nbins, s);
-        if (M > 0) {
+        if (vblocks > 0) {
             if (grid)
                 hipLaunchKernelGGL((k_bin_scatter<R, true>), dim3(vblocks), dim3(kAggThreads), 0, s, uvw,
-                                   static_cast<const cpx<R>*>(in), (long long)M, P, (const uint32_t*)start, cursor,
-                                   rec_bin);
+                                   static_cast<const cpx<R>*>(in), (const long long*)coff, (const int*)cblk, P,
+                                   (const uint32_t*)start, cursor, rec_bin);
             else
                 hipLaunchKernelGGL((k_bin_scatter<R, false>), dim3(vblocks), dim3(kAggThreads), 0, s, uvw,
-                                   (const cpx<R>*)nullptr, (long long)M, P, (const uint32_t*)start, cursor, rec_bin);
+                                   (const cpx<R>*)nullptr, (const long long*)coff, (const int*)cblk, P,
+                                   (const uint32_t*)start, cursor, rec_bin);
             hipLaunchKernelGGL(k_bin_local_sort<R>, dim3(L.nbins), dim3(256), 0, s, (const Rec<R>*)rec_bin, rec,
                                (const uint32_t*)start, cls, P);
         }
-        fill<uint8_t>(rows, size_t(P.nbt) * P.nbr, uint8_t(0), s);
+        fill<uint8_t>(rows, size_t(L.nch) * P.nbt * P.nbr, uint8_t(0), s);
         hipLaunchKernelGGL(k_tile_occupancy, dim3((L.nbins + 255) / 256), dim3(256), 0, s, (const uint32_t*)start,
                            (const uint32_t*)cls, P, occ, rows);
     }
-    // Layer passes: the stack and FFT buffers hold L.pass_layers layers at a
-    // time.  Grid: each pass scatters into its tiles and transforms them; the
-    // first pass writes the dirty map, later ones add to it.  Degrid: each pass
-    // transforms its layers and gathers from its tiles; every (visibility, tile)
-    // part belongs to exactly one pass, and k_degrid_finish sums them at the end.
+    // Layer passes over the virtual layer axis (channel c's layers start at
+    // c nbt kTileT): the stack and FFT buffers hold L.pass_layers layers at a
+    // time.  Grid: each pass scatters into its tiles and transforms them; a
+    // channel's first layers write its map, later ones add to it.  Degrid: each
+    // pass transforms its layers and gathers from its tiles; every (visibility,
+    // tile) part belongs to exactly one pass, and k_degrid_finish sums them at
+    // the end.  Virtual layers past a channel's n_layers are padding, skipped.
     const int per_layer = P.nbs * P.nbr;
     auto* part = reinterpret_cast<cpx<R>*>(w + L.part);
-    for (int pl0 = 0; pl0 < P.n_layers; pl0 += L.pass_layers) {
+    for (int pl0 = 0; pl0 < L.last_layer; pl0 += L.pass_layers) {
         DevParams Q = P;
         Q.pl0 = pl0;
-        Q.pln = std::min(L.pass_layers, P.n_layers - pl0);
+        Q.pln = std::min(L.pass_layers, L.last_layer - pl0);
         const int nblocks = ((Q.pln + kTileT - 1) / kTileT) * per_layer;
         if (grid) {
             {
@@ -574,24 +648,43 @@ size_t grid_workspace_bytes_min(const wsg_plan* plan, int prec, int64_t M) {
     return layout_of(plan, prec, M, 1).total;
 }
 
-int grid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* vis, void* dirty,
-                      void* ws, size_t ws_bytes, void* stream) {
+size_t grid_workspace_bytes_batch(const wsg_plan* plan, int prec, int nch, int64_t M, int min_passes) {
+    if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL || nch < 1 ||
+        nch > kMaxChannels)
+        return 0;
+    return layout_of(plan, prec, M, min_passes ? 1 : nch * plan->nbt, nch).total;
+}
+
+int grid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int64_t* M, const double* uvw,
+                            const void* vis, void* dirty, void* ws, size_t ws_bytes, void* stream) {
     Layout L;
-    int rc = check_call(plan, prec, M, uvw, vis, true, dirty, false, ws, ws_bytes, &L);
+    int64_t tot = 0;
+    int rc = check_call(plan, prec, nch, M, &tot, uvw, vis, true, dirty, false, ws, ws_bytes, &L);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return prec == WSG_F32 ? run<float>(plan, true, M, uvw, vis, dirty, ws, L, s)
-                           : run<double>(plan, true, M, uvw, vis, dirty, ws, L, s);
+    return prec == WSG_F32 ? run<float>(plan, true, M, tot, uvw, vis, dirty, ws, L, s)
+                           : run<double>(plan, true, M, tot, uvw, vis, dirty, ws, L, s);
+}
+
+int degrid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int64_t* M, const double* uvw,
+                              const void* image, void* vis, void* ws, size_t ws_bytes, void* stream) {
+    Layout L;
+    int64_t tot = 0;
+    int rc = check_call(plan, prec, nch, M, &tot, uvw, image, false, vis, true, ws, ws_bytes, &L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return prec == WSG_F32 ? run<float>(plan, false, M, tot, uvw, image, vis, ws, L, s)
+                           : run<double>(plan, false, M, tot, uvw, image, vis, ws, L, s);
+}
+
+int grid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* vis, void* dirty,
+                      void* ws, size_t ws_bytes, void* stream) {
+    return grid_visibilities_batch(plan, prec, 1, &M, uvw, vis, dirty, ws, ws_bytes, stream);
 }
 
 int degrid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* image, void* vis,
                         void* ws, size_t ws_bytes, void* stream) {
-    Layout L;
-    int rc = check_call(plan, prec, M, uvw, image, false, vis, true, ws, ws_bytes, &L);
-    if (rc) return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    return prec == WSG_F32 ? run<float>(plan, false, M, uvw, image, vis, ws, L, s)
-                           : run<double>(plan, false, M, uvw, image, vis, ws, L, s);
+    return degrid_visibilities_batch(plan, prec, 1, &M, uvw, image, vis, ws, ws_bytes, stream);
 }
 
 int64_t grid_skipped(const wsg_plan* plan, const void* ws, void* stream) {

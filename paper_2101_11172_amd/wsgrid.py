@@ -22,6 +22,7 @@ WSG_OK, WSG_EINVAL, WSG_EWORKSPACE, WSG_ENOMEM, WSG_EHIP = 0, -1, -2, -3, -4
 _lib = None
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_int64_p = ctypes.POINTER(ctypes.c_int64)
 
 _SIGNATURES = {
     "grid_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
@@ -38,6 +39,14 @@ _SIGNATURES = {
     "degrid_visibilities": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                            ctypes.c_void_p]),
+    "grid_visibilities_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int64_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_size_t, ctypes.c_void_p]),
+    "degrid_visibilities_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int64_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_size_t, ctypes.c_void_p]),
+    "grid_workspace_bytes_batch": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                                     ctypes.c_int]),
     "grid_skipped": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "grid_last_error": (ctypes.c_char_p, []),
     "wsg_design_eval": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_double_p, _c_double_p,
@@ -131,6 +140,29 @@ def degrid_visibilities(plan: int, prec: int, M: int, uvw_ptr: int, image_ptr: i
          "degrid_visibilities")
 
 
+def _counts(M) -> ctypes.Array:
+    return (ctypes.c_int64 * len(M))(*[int(m) for m in M])
+
+
+def grid_workspace_bytes_batch(plan: int, prec: int, nch: int, M: int, min_passes: bool = False) -> int:
+    n = lib().grid_workspace_bytes_batch(plan, prec, nch, M, 1 if min_passes else 0)
+    if n == 0:
+        raise RuntimeError("grid_workspace_bytes_batch: bad argument")
+    return n
+
+
+def grid_visibilities_batch(plan: int, prec: int, M, uvw_ptr: int, vis_ptr: int, dirty_ptr: int,
+                            ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _err(lib().grid_visibilities_batch(plan, prec, len(M), _counts(M), uvw_ptr, vis_ptr, dirty_ptr, ws_ptr,
+                                       ws_bytes, stream), "grid_visibilities_batch")
+
+
+def degrid_visibilities_batch(plan: int, prec: int, M, uvw_ptr: int, image_ptr: int, vis_ptr: int,
+                              ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _err(lib().degrid_visibilities_batch(plan, prec, len(M), _counts(M), uvw_ptr, image_ptr, vis_ptr, ws_ptr,
+                                         ws_bytes, stream), "degrid_visibilities_batch")
+
+
 def grid_skipped(plan: int, ws_ptr: int, stream: int) -> int:
     n = lib().grid_skipped(plan, ws_ptr, stream)
     if n < 0:
@@ -220,10 +252,10 @@ class Plan:
         except Exception:
             pass
 
-    def workspace(self, prec: int, M: int) -> torch.Tensor:
-        need = grid_workspace_bytes(self._p, prec, M)
+    def workspace(self, prec: int, M: int, nch: int = 1) -> torch.Tensor:
+        need = grid_workspace_bytes_batch(self._p, prec, nch, M)
         if self.max_workspace_bytes is not None and need > self.max_workspace_bytes:
-            need = max(grid_workspace_bytes_min(self._p, prec, M), int(self.max_workspace_bytes))
+            need = max(grid_workspace_bytes_batch(self._p, prec, nch, M, True), int(self.max_workspace_bytes))
         ws = self._ws.get(prec)
         if ws is None or ws.numel() < need:
             self._ws.pop(prec, None)
@@ -267,6 +299,51 @@ class Plan:
         ws = self.workspace(prec, M)
         degrid_visibilities(self._p, prec, M, uvw.data_ptr(), image.data_ptr(), out.data_ptr(), ws.data_ptr(),
                             ws.numel(), torch.cuda.current_stream(self.device).cuda_stream)
+        return out
+
+    def grid_batch(self, uvw: torch.Tensor, counts, vis: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Dirty maps [len(counts), N, N] of channels whose visibilities are
+        consecutive runs of counts[c] rows of uvw / entries of vis."""
+        M = self._check_uvw(uvw)
+        counts = [int(c) for c in counts]
+        if sum(counts) != M:
+            raise ValueError("counts must add up to the number of visibilities")
+        if vis.dtype not in (torch.complex64, torch.complex128) or vis.shape != (M,) or not vis.is_contiguous() \
+                or vis.device != self.device:
+            raise ValueError("vis must be a contiguous complex64/complex128 [M] tensor on the plan's device")
+        prec = _PREC[vis.dtype]
+        rdt = torch.float32 if prec == WSG_F32 else torch.float64
+        shape = (len(counts), self.N, self.N)
+        if out is None:
+            out = torch.empty(shape, dtype=rdt, device=self.device)
+        elif out.dtype != rdt or out.shape != shape or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or shape")
+        ws = self.workspace(prec, M, len(counts))
+        grid_visibilities_batch(self._p, prec, counts, uvw.data_ptr(), vis.data_ptr(), out.data_ptr(),
+                                ws.data_ptr(), ws.numel(), torch.cuda.current_stream(self.device).cuda_stream)
+        return out
+
+    def degrid_batch(self, uvw: torch.Tensor, counts, image: torch.Tensor,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+        """Model visibilities of channels c = 0.. from images [len(counts), N, N],
+        concatenated in channel order."""
+        M = self._check_uvw(uvw)
+        counts = [int(c) for c in counts]
+        if sum(counts) != M:
+            raise ValueError("counts must add up to the number of visibilities")
+        shape = (len(counts), self.N, self.N)
+        if image.dtype not in (torch.float32, torch.float64) or image.shape != shape \
+                or not image.is_contiguous() or image.device != self.device:
+            raise ValueError("image must be a contiguous float32/float64 [channels, N, N] tensor on the device")
+        prec = _PREC[image.dtype]
+        cdt = torch.complex64 if prec == WSG_F32 else torch.complex128
+        if out is None:
+            out = torch.empty(M, dtype=cdt, device=self.device)
+        elif out.dtype != cdt or out.shape != (M,) or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or shape")
+        ws = self.workspace(prec, M, len(counts))
+        degrid_visibilities_batch(self._p, prec, counts, uvw.data_ptr(), image.data_ptr(), out.data_ptr(),
+                                  ws.data_ptr(), ws.numel(), torch.cuda.current_stream(self.device).cuda_stream)
         return out
 
     def skipped(self, prec: int) -> int:
