@@ -225,6 +225,71 @@ def timed(step, steps: int):
     return (t1 - t0) * 1e3 / steps, wsgrid.wsg_stage_times()
 
 
+def channels_main(args) -> int:
+    """One grid_visibilities_batch plus one degrid_visibilities_batch of 32
+    channels (1.0-1.8 GHz on the wide-field array, 4-10M visibilities each
+    after random flagging, 224M in all) on one 2048^2 plan, FP32."""
+    import numpy as np
+    import torch
+
+    from paper_2101_11172_amd import inputs, wsgrid
+
+    dev = torch.device("cuda", 0)
+    log("generating the batched-channel workload")
+    w = inputs.channels_workload()
+    N, L, W, x0, wmax, counts = w["N"], w["L"], w["W"], w["x0"], w["wmax"], w["counts"]
+    M, C = int(sum(counts)), len(counts)
+    uvw = torch.from_numpy(w["uvw"]).to(dev)
+    vis = torch.from_numpy(w["vis"]).to(dev)
+    del w
+    plan = wsgrid.Plan(N, L, W, x0, wmax, device=dev, max_workspace_bytes=int(args.max_workspace_gb * (1 << 30)))
+    info = plan.info
+    img = torch.from_numpy(np.stack([inputs.random_image(N, 200 + c).astype(np.float32) for c in range(C)])).to(dev)
+    out_img = torch.empty((C, N, N), dtype=torch.float32, device=dev)
+    out_vis = torch.empty(M, dtype=torch.complex64, device=dev)
+    log(f"channels={C} M={M} (per channel {min(counts)}..{max(counts)}) N={N} N'={info['Nprime']} "
+        f"layers={info['n_layers']}")
+
+    def step():
+        plan.grid_batch(uvw, counts, vis, out=out_img)
+        plan.degrid_batch(uvw, counts, img, out=out_vis)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    ws_bytes = plan.workspace(wsgrid.WSG_F32, M, C).numel()
+    last_layer = (C - 1) * 16 * ((info["n_layers"] + 15) // 16) + info["n_layers"]
+    per_pass = wsgrid.grid_layers_per_pass(plan._p, wsgrid.WSG_F32, C, M, ws_bytes)
+    passes = -(-last_layer // per_pass)
+    ms, stages = timed(step, args.steps)
+    log(f"channels: {ms:.3f} ms/step, {M / (ms * 1e-3):.4e} vis/s, {passes} layer passes")
+    result = {
+        "metric": "batched channels: visibilities/s grid+degrid, 32 channels in one call per direction",
+        "value": M / (ms * 1e-3),
+        "unit": "visibilities/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"batched channels: {C} channels 1.0-1.8 GHz of the wide-field array (64 antennas, "
+                                f"+-1 h), 0-60% random flagging per channel, {M} visibilities ({min(counts)}-"
+                                f"{max(counts)} per channel), one {N}x{N} plan, L={L}, W={W}, x0={x0}, "
+                                f"{info['n_layers']} w-layers per channel, {passes} layer passes"),
+                   "channels": C, "visibilities": M, "N": N, "w_layers": info["n_layers"],
+                   "workspace_bytes": ws_bytes, "layer_passes": passes},
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+    }
+    print(json.dumps(result), flush=True)
+    plan.close()
+    return 0
+
+
 def imaging_main(args) -> int:
     """One gradient step of ||degrid(I) - V||^2 per step: DegridFn forward
     (degrid_visibilities) and backward (grid_visibilities) on a 4096^2 FP32
@@ -261,11 +326,8 @@ def imaging_main(args) -> int:
         step()
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{args.warmup} done")
-    full = wsgrid.grid_workspace_bytes(plan._p, wsgrid.WSG_F32, M)
-    least = wsgrid.grid_workspace_bytes_min(plan._p, wsgrid.WSG_F32, M)
-    per_tile_layer = (full - least) // max(1, (info["n_layers"] + 15) // 16 - 1)
-    tiles_per_pass = 1 + (plan.workspace(wsgrid.WSG_F32, M).numel() - least) // per_tile_layer
-    passes = -(-((info["n_layers"] + 15) // 16) // tiles_per_pass)
+    per_pass = wsgrid.grid_layers_per_pass(plan._p, wsgrid.WSG_F32, 1, M, plan.workspace(wsgrid.WSG_F32, M).numel())
+    passes = -(-info["n_layers"] // per_pass)
     ms, _ = timed(step, args.steps)
     log(f"imaging: {ms:.3f} ms/step, {M / (ms * 1e-3):.4e} vis/s, {passes} layer passes")
     # stage breakdown from the same two calls made on this thread (autograd runs
@@ -318,9 +380,11 @@ def main() -> int:
                     help="first run one device-to-device copy of this many GB (counter calibration)")
     ap.add_argument("--no-z-offset", action="store_true",
                     help="widefield: the planner variant without z offset (Sec. 5.3; about twice the layers)")
-    ap.add_argument("--workload", choices=("widefield", "imaging"), default="widefield",
-                    help="imaging: one differentiable-imaging gradient step per step (4096^2, 50M visibilities)")
-    ap.add_argument("--max-workspace-gb", type=float, default=96.0, help="imaging: workspace cap (layer passes)")
+    ap.add_argument("--workload", choices=("widefield", "imaging", "channels"), default="widefield",
+                    help="imaging: one differentiable-imaging gradient step per step (4096^2, 50M visibilities); "
+                         "channels: one batched grid + degrid of 32 channels per step")
+    ap.add_argument("--max-workspace-gb", type=float, default=96.0,
+                    help="imaging and channels: workspace cap (layer passes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path is built and measured on a single MI355X "
@@ -328,6 +392,8 @@ def main() -> int:
         return 2
     if args.workload == "imaging":
         return imaging_main(args)
+    if args.workload == "channels":
+        return channels_main(args)
 
     import numpy as np
     import torch

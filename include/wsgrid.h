@@ -176,6 +176,15 @@ int degrid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int
 size_t grid_workspace_bytes_batch(const wsg_plan* plan, int prec, int nch, int64_t M, int min_passes);
 
 /*
+ * Virtual w-layers per layer pass that a call with nch channels, M
+ * visibilities in all and a workspace of ws_bytes would use (the channels'
+ * layers laid end to end, each channel padded to whole tile layers of 16);
+ * WSG_EWORKSPACE when ws_bytes is below the minimum, WSG_EINVAL on a bad
+ * argument.  Host only.
+ */
+int grid_layers_per_pass(const wsg_plan* plan, int prec, int nch, int64_t M, size_t ws_bytes);
+
+/*
  * Number of visibilities skipped (|w| > wmax or non-finite) by the last call
  * that used workspace `ws`.  Waits for `stream`.  Returns < 0 on error.
  */

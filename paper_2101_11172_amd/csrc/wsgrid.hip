@@ -648,6 +648,17 @@ size_t grid_workspace_bytes_min(const wsg_plan* plan, int prec, int64_t M) {
     return layout_of(plan, prec, M, 1).total;
 }
 
+int grid_layers_per_pass(const wsg_plan* plan, int prec, int nch, int64_t M, size_t ws_bytes) {
+    if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL || nch < 1 ||
+        nch > kMaxChannels)
+        return fail(WSG_EINVAL, "bad argument");
+    int tiles = nch * plan->nbt;
+    Layout L = layout_of(plan, prec, M, tiles, nch);
+    while (tiles > 1 && ws_bytes < L.total) L = layout_of(plan, prec, M, --tiles, nch);
+    if (ws_bytes < L.total) return fail(WSG_EWORKSPACE, "workspace too small");
+    return L.pass_layers;
+}
+
 size_t grid_workspace_bytes_batch(const wsg_plan* plan, int prec, int nch, int64_t M, int min_passes) {
     if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL || nch < 1 ||
         nch > kMaxChannels)

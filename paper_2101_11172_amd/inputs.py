@@ -18,6 +18,12 @@ Workloads (all seeded with ``numpy.random.default_rng``):
   i.e. the image is Nyquist-sampled; complex N(0, 1) values (complex64 or
   complex128); W = 7, x0 = 0.25.
 * ``lowcost`` -- the ``widefield`` geometry with W = 4, x0 = 0.5.
+* ``channels`` (``channels_workload``) -- the ``widefield`` array observed in
+  32 channels at f_c = 1.0 + 0.8 c / 31 GHz: uvw of the 1.4 GHz tracks scaled
+  by f_c / 1.4 GHz, then all channels by one factor so that the 1.8 GHz
+  channel has max(|u|, |v|) = 0.95 N / (2 L) (N = 2048, L = 0.4); each channel
+  flags a fraction U(0, 0.6) of its visibilities (Bernoulli per visibility),
+  so the channels hold 4-10M visibilities each; complex N(0, 1) values.
 """
 from __future__ import annotations
 
@@ -87,6 +93,26 @@ def scale_to_image(uvw: np.ndarray, N: int, L: float, fill: float = 0.95) -> np.
     """Scale all of uvw so that max(|u|, |v|) = fill * N / (2 L) (Nyquist-sampled image)."""
     umax = np.max(np.abs(uvw[:, :2]))
     return uvw * (fill * N / (2.0 * L) / umax)
+
+
+def channels_workload(n_channels: int = 32, n_dumps: int = 4960, seed: int = 3, vis_dtype=np.complex64) -> dict:
+    """Batched-channel workload (see module docstring): concatenated uvw and
+    values in channel order, with the per-channel counts."""
+    rng = np.random.default_rng(seed)
+    N, L = 2048, 0.4
+    base = array_uvw(64, 5000.0, -30.0, -30.0, 1.0, n_dumps, 1.4e9, 1)
+    freqs = 1.0e9 + 0.8e9 * np.arange(n_channels) / max(1, n_channels - 1)
+    top = np.max(np.abs(base[:, :2])) * freqs[-1] / 1.4e9
+    scale = 0.95 * N / (2.0 * L) / top
+    uvws, counts = [], []
+    for f in freqs:
+        keep = rng.uniform(size=base.shape[0]) >= rng.uniform(0.0, 0.6)
+        uvws.append(base[keep] * (scale * f / 1.4e9))
+        counts.append(int(np.count_nonzero(keep)))
+    uvw = np.concatenate(uvws)
+    wmax = float(np.max(np.abs(uvw[:, 2])))
+    return dict(name="channels", N=N, L=L, W=7, x0=0.25, wmax=wmax, uvw=uvw, counts=counts, freqs=freqs,
+                vis=random_vis(uvw.shape[0], seed + 100, vis_dtype))
 
 
 def workload(name: str, seed: int | None = None, n_dumps: int = 4960,

@@ -47,6 +47,8 @@ _SIGNATURES = {
                                                  ctypes.c_size_t, ctypes.c_void_p]),
     "grid_workspace_bytes_batch": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                                      ctypes.c_int]),
+    "grid_layers_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                            ctypes.c_size_t]),
     "grid_skipped": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "grid_last_error": (ctypes.c_char_p, []),
     "wsg_design_eval": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_double_p, _c_double_p,
@@ -148,6 +150,13 @@ def grid_workspace_bytes_batch(plan: int, prec: int, nch: int, M: int, min_passe
     n = lib().grid_workspace_bytes_batch(plan, prec, nch, M, 1 if min_passes else 0)
     if n == 0:
         raise RuntimeError("grid_workspace_bytes_batch: bad argument")
+    return n
+
+
+def grid_layers_per_pass(plan: int, prec: int, nch: int, M: int, ws_bytes: int) -> int:
+    n = lib().grid_layers_per_pass(plan, prec, nch, M, ws_bytes)
+    if n <= 0:
+        raise RuntimeError(f"grid_layers_per_pass failed: {grid_last_error()}")
     return n
 
 

@@ -90,6 +90,7 @@ def test_batch_layer_passes_cross_channels(case):
     M = int(sum(counts))
     least = wg.grid_workspace_bytes_batch(full._p, wg.WSG_F64, len(counts), M, True)
     assert least < wg.grid_workspace_bytes_batch(full._p, wg.WSG_F64, len(counts), M)
+    assert wg.grid_layers_per_pass(full._p, wg.WSG_F64, len(counts), M, least) == 16
     small = wg.Plan(N, L, W, x0, wmax, device=DEV, max_workspace_bytes=least)
     v = torch.from_numpy(vis).to(DEV)
     im = torch.from_numpy(imgs).to(DEV)

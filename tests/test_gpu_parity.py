@@ -251,6 +251,7 @@ def test_layer_passes():
             g = gpu_grid(plan, uvw, vis, prec)
             d = gpu_degrid(plan, uvw, img, prec)
             assert plan.workspace(code, M).numel() == cap
+            assert wg.grid_layers_per_pass(plan._p, code, 1, M, cap) == (16 if cap == least else 48)
             plan.close()
             assert rel(g, ref_g) <= tol, (prec, cap, "grid", rel(g, ref_g))
             assert rel(d, ref_d) <= tol, (prec, cap, "degrid", rel(d, ref_d))
