@@ -249,6 +249,12 @@ def channels_main(args) -> int:
     out_vis = torch.empty(M, dtype=torch.complex64, device=dev)
     log(f"channels={C} M={M} (per channel {min(counts)}..{max(counts)}) N={N} N'={info['Nprime']} "
         f"layers={info['n_layers']}")
+    tuned = None
+    if args.autotune:
+        from paper_2101_11172_amd.autotune import tune_pass_layers
+        tuned = tune_pass_layers(plan, uvw, counts, vis, img, plan.max_workspace_bytes)
+        plan.max_workspace_bytes = tuned["workspace_bytes"]
+        log(f"autotune: {tuned['pass_layers']} layers per pass, ms by pass size {tuned['ms']}")
 
     def step():
         plan.grid_batch(uvw, counts, vis, out=out_img)
@@ -283,6 +289,7 @@ def channels_main(args) -> int:
                                 f"{info['n_layers']} w-layers per channel, {passes} layer passes"),
                    "channels": C, "visibilities": M, "N": N, "w_layers": info["n_layers"],
                    "workspace_bytes": ws_bytes, "layer_passes": passes},
+        "autotune": tuned,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
     }
     print(json.dumps(result), flush=True)
@@ -385,6 +392,8 @@ def main() -> int:
                          "channels: one batched grid + degrid of 32 channels per step")
     ap.add_argument("--max-workspace-gb", type=float, default=96.0,
                     help="imaging and channels: workspace cap (layer passes)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="channels: choose the layers per pass within the cap by timing (autotune.py) first")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path is built and measured on a single MI355X "

@@ -1,0 +1,64 @@
+"""Plane-batch autotuner for (batched) gridding and degridding.
+
+The library takes the w-layers of all channels in passes whose size is set by
+the workspace it is given (grid_layers_per_pass).  More layers per pass means
+fewer, larger launches and more memory; fewer means more passes over the
+binned records.  ``tune_pass_layers`` times one batched grid plus one batched
+degrid for a few workspace sizes between the smallest the call accepts and a
+memory cap, and returns the fastest.  The 16 x 16 x 16 tile of the scatter and
+gather kernels is fixed at compile time by their LDS budget and is not tuned.
+
+Host logic and timing only: every call runs the library's own kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import wsgrid as wg
+
+
+def tune_pass_layers(plan: "wg.Plan", uvw: torch.Tensor, counts, vis: torch.Tensor, image: torch.Tensor,
+                     max_workspace_bytes: int, n_candidates: int = 4, repeats: int = 2) -> dict:
+    """Fastest workspace size (and its layers per pass) for these inputs.
+
+    uvw, vis: concatenated channels (counts[c] visibilities each); image:
+    [len(counts), N, N] of the matching real precision.  Returns
+    {"workspace_bytes", "pass_layers", "ms": {pass_layers: ms per grid + degrid}}.
+    """
+    counts = [int(c) for c in counts]
+    nch, M = len(counts), int(sum(counts))
+    prec = wg.WSG_F32 if vis.dtype == torch.complex64 else wg.WSG_F64
+    rdt = torch.float32 if prec == wg.WSG_F32 else torch.float64
+    least = wg.grid_workspace_bytes_batch(plan._p, prec, nch, M, True)
+    top = min(wg.grid_workspace_bytes_batch(plan._p, prec, nch, M), int(max_workspace_bytes))
+    if top < least:
+        raise ValueError(f"the cap is below the smallest workspace ({least} bytes)")
+    sizes = sorted({least + (top - least) * i // max(1, n_candidates - 1) for i in range(n_candidates)})
+    by_layers = {}
+    for b in sizes:      # keep the smallest workspace that gives each pass size
+        by_layers.setdefault(wg.grid_layers_per_pass(plan._p, prec, nch, M, b), b)
+    stream = torch.cuda.current_stream(plan.device)
+    dirty = torch.empty((nch, plan.N, plan.N), dtype=rdt, device=plan.device)
+    out = torch.empty(M, dtype=vis.dtype, device=plan.device)
+    timings = {}
+    for layers, nbytes in sorted(by_layers.items()):
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=plan.device)
+
+        def step():
+            wg.grid_visibilities_batch(plan._p, prec, counts, uvw.data_ptr(), vis.data_ptr(), dirty.data_ptr(),
+                                       ws.data_ptr(), nbytes, stream.cuda_stream)
+            wg.degrid_visibilities_batch(plan._p, prec, counts, uvw.data_ptr(), image.data_ptr(), out.data_ptr(),
+                                         ws.data_ptr(), nbytes, stream.cuda_stream)
+
+        step()                                              # warm-up
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(repeats):
+            step()
+        end.record(stream)
+        end.synchronize()
+        timings[layers] = start.elapsed_time(end) / repeats
+        del ws
+        torch.cuda.empty_cache()      # the next candidate may need the memory back
+    best = min(timings, key=timings.get)
+    return {"workspace_bytes": by_layers[best], "pass_layers": best, "ms": timings}

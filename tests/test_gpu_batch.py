@@ -118,3 +118,25 @@ def test_batch_rejects_bad_arguments():
         wg.grid_visibilities_batch(plan._p, wg.WSG_F32, [0] * 65, uvw.data_ptr(), vis.data_ptr(), out.data_ptr(),
                                    ws.data_ptr(), ws.numel(), torch.cuda.current_stream(DEV).cuda_stream)
     plan.close()
+
+
+def test_autotuner_picks_a_working_pass_size():
+    from paper_2101_11172_amd.autotune import tune_pass_layers
+
+    N, L, W, x0, wmax, counts = CASES[1]
+    uvws = channels(N, L, wmax, counts, 41)
+    M = int(sum(counts))
+    uvw = torch.from_numpy(np.concatenate(uvws)).to(DEV)
+    vis = torch.from_numpy(inputs.random_vis(M, 42)).to(DEV, torch.complex64)
+    img = torch.from_numpy(np.stack([inputs.random_image(N, 43 + c) for c in range(len(counts))])).to(DEV,
+                                                                                                      torch.float32)
+    plan = wg.Plan(N, L, W, x0, wmax, device=DEV)
+    cap = wg.grid_workspace_bytes_batch(plan._p, wg.WSG_F32, len(counts), M)
+    res = tune_pass_layers(plan, uvw, counts, vis, img, cap)
+    assert len(res["ms"]) >= 2 and res["pass_layers"] in res["ms"]
+    assert wg.grid_layers_per_pass(plan._p, wg.WSG_F32, len(counts), M, res["workspace_bytes"]) == res["pass_layers"]
+    ref = plan.degrid_batch(uvw, counts, img)
+    tuned = wg.Plan(N, L, W, x0, wmax, device=DEV, max_workspace_bytes=res["workspace_bytes"])
+    assert torch.equal(tuned.degrid_batch(uvw, counts, img), ref)
+    tuned.close()
+    plan.close()
