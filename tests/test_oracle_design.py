@@ -2,7 +2,7 @@
 
 Each check is fixed by the paper or by mathematics, not by re-running the
 oracle's own formulas:
-* Sec. 6.2 prints E = 1.3e-7 for W = 7, x0 = 0.25;
+* Sec. 6.1 prints E = 1.3e-7 for W = 7, x0 = 0.25;
 * Sec. 6.3 (Fig. rms_relative_error) and Sec. 8: E falls steeply with W; smaller
   x0 makes it fall faster; x0 = 1/3 costs about an order of magnitude at W = 7;
 * Sec. 6.2 (original method): with a top hat C and h = 1/sinc,
@@ -22,7 +22,7 @@ from oracle.kernel_design import LeastMisfit, error_bound, least_misfit, map_err
 
 
 def test_error_bound_printed_value():
-    # Sec. 6.2: least-misfit, x0 = 0.25, W = 7 achieves E = 1.3e-7
+    # Sec. 6.1: least-misfit, x0 = 0.25, W = 7 achieves E = 1.3e-7
     E = least_misfit(7, 0.25).E
     assert 1.2e-7 <= E <= 1.4e-7, E
 
