@@ -111,6 +111,15 @@ def test_lowcost_against_dft_and_fp64():
     e64, e32 = rel(v64[idx], exact), rel(v32[idx], exact)
     print(f"lowcost degrid vs DFT: fp64 {e64:.3e} fp32 {e32:.3e}, E = {plan.info['E']:.3e}")
     assert e64 <= 2 * np.sqrt(3) * plan.info["E"] and abs(e32 - e64) <= 1e-4
+    # the dirty map at 16 sampled pixels
+    rng = np.random.default_rng(10)
+    rows, cols = rng.integers(0, w["N"], 16), rng.integers(0, w["N"], 16)
+    exact_g = dft.dft_grid(op, w["uvw"], w["vis"], rows=rows, cols=cols, chunk=8)
+    g64 = plan.grid(t_uvw, torch.from_numpy(w["vis"]).to(DEV)).cpu().numpy()
+    g32 = plan.grid(t_uvw, torch.from_numpy(w["vis"]).to(DEV, torch.complex64)).cpu().double().numpy()
+    f64, f32 = rel(g64[rows, cols], exact_g), rel(g32[rows, cols], exact_g)
+    print(f"lowcost grid vs DFT at 16 pixels: fp64 {f64:.3e} fp32 {f32:.3e}")
+    assert f64 <= 2 * np.sqrt(3) * plan.info["E"] and abs(f32 - f64) <= 1e-4
     plan.close()
 
 
