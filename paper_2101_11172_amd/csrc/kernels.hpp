@@ -944,7 +944,9 @@ struct FftCfg {
 // layer and row of tiles (kTileR stack rows, taken NL at a time); the next NL
 // rows are loaded while the current ones are transformed.  Unmarked tiles are
 // read as zero; a row of tiles with none marked is neither transformed nor
-// written (its lines are zero).
+// written (its lines are zero).  Layer t of the pass is virtual layer
+// t + t_base; in a batched call (chl = the channels' layer stride, else 0) a
+// padding layer (virtual layer mod chl >= n_layers) is skipped.
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_grid_fft_a(const cpx<R>* __restrict__ stack, const uint8_t* __restrict__ occ, cpx<R>* __restrict__ inter,
@@ -996,6 +998,9 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
 // grid pass B: IFFT along r of intermediate rows [t][q][:] for every layer t,
 // w-screen exp(+i 2 pi t z) and accumulation of the real part in registers
 // (Algorithm 5 steps 3b-4), then the 3-D correction (step 5): dirty[q][p].
+// One launch covers a segment of P.pln consecutive layers of one channel: the
+// segment starts at layer seg0 of the pass's buffer and at layer tloc0 of the
+// channel; `accumulate` adds to the map instead of writing it.
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
     k_grid_fft_b(const cpx<R>* __restrict__ inter, const cpx<R>* __restrict__ tw, const R* __restrict__ corr,
@@ -1053,6 +1058,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 
 // degrid pass B': for each image row q and layer t: f h_x h_y h_z exp(-i 2 pi t z)
 // zero-padded along p, FFT along p -> intermediate [t][q][r] (Algorithm 6 steps 2-3).
+// Segments of one channel's layers as for k_grid_fft_b.
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
     k_degrid_fft_b(const R* __restrict__ image, const R* __restrict__ corr, const cpx<R>* __restrict__ tw,
@@ -1103,7 +1109,8 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 // row [t][r][s].  One block per layer and row of tiles (kTileR lines, taken NL
 // at a time); the next NL lines are loaded while the current ones are
 // transformed.  Only marked tiles are stored (the gather reads no other); a row
-// of tiles with none marked is skipped.
+// of tiles with none marked is skipped.  Layers and padding layers as for
+// k_grid_fft_a.
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     k_degrid_fft_a(const cpx<R>* __restrict__ inter, const uint8_t* __restrict__ occ, const cpx<R>* __restrict__ tw,

@@ -13,6 +13,11 @@
 //                      k_degrid_fft_a (pad, FFT along q, occupied tiles) ->
 //                      k_degrid_tiles (3-D gather, one part per tile reached) ->
 //                      k_degrid_finish (sum of parts, phase, fold) -> vis [M]
+// Everything after binning runs once per layer pass when the workspace holds
+// fewer layers than the plan has (k_degrid_finish once, at the end).  Batched
+// calls put the channels' layers end to end on one virtual layer axis: one
+// launch per stage covers all channels, except the pass-B FFTs, which run per
+// channel segment (each has its own map).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
