@@ -101,9 +101,16 @@ def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict) 
 
 
 def source_digest() -> str:
+    """Digest of the device sources with comments and blank space removed, so
+    that a comment edit does not disown the counters taken on them."""
+    import re
+
     h = hashlib.sha256()
     for f in ("kernels.hpp", "fft.hpp", "common.hpp", "wsgrid.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2101_11172_amd", "csrc", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_2101_11172_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
