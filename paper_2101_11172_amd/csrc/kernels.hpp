@@ -788,7 +788,8 @@ struct GatherCfg {
 template <typename R, int W>
 __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__ rec,
                                                       const uint32_t* __restrict__ start,
-                                                      const uint32_t* __restrict__ cls, DevParams P,
+                                                      const uint32_t* __restrict__ cls,
+                                                      const uint8_t* __restrict__ occ, DevParams P,
                                                       const R* __restrict__ coef_g,
                                                       const cpx<R>* __restrict__ stack, cpx<R>* __restrict__ part,
                                                       size_t part_stride) {
@@ -800,6 +801,7 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     __shared__ TileSegs sg;
 
     const int tile = tile_of_block(P);
+    if (!occ[tile]) return;     // no visibility reaches it
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0 % (P.nbt * kTileT));   // layers of its channel

@@ -196,7 +196,7 @@ void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* s
         hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, occ, P, coef,
                            stack);
     else
-        hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, P, coef,
+        hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, occ, P, coef,
                            (const cpx<R>*)stack, part, part_stride);
 }
 
