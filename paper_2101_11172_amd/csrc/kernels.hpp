@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
 // (degrid).  A row of tiles (t tile, u tile) is marked in `rows` when one of
 // its tiles is (`rows` zero on entry; racing stores all write 1).
 __global__ void k_tile_occupancy(const uint32_t* __restrict__ start, const uint32_t* __restrict__ cls, DevParams P,
-                                 uint8_t* __restrict__ occ, uint8_t* __restrict__ rows) {
+                                 uint8_t* __restrict__ occ, uint8_t* __restrict__ rows, uint32_t* __restrict__ flag) {
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
     const int nt = P.nch * P.nbt * P.nbs * P.nbr;
     if (tile >= nt) return;
@@ -410,7 +410,16 @@ __global__ void k_tile_occupancy(const uint32_t* __restrict__ start, const uint3
         }
     }
     occ[tile] = any ? 1 : 0;
+    flag[tile] = any ? 1u : 0u;
     if (any) rows[bt * P.nbr + br] = 1;
+}
+
+// The occupied tiles in tile order: list[pos[t]] = t for every marked tile t,
+// pos the exclusive scan of the flags (pos[n] = number of marked tiles).
+__global__ void k_tile_list(const uint8_t* __restrict__ occ, const uint32_t* __restrict__ pos, int n,
+                            uint32_t* __restrict__ list) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n && occ[t]) list[pos[t]] = uint32_t(t);
 }
 
 // ------------------------------------------------ 3-D scatter / gather tiles --
@@ -504,12 +513,18 @@ __device__ __forceinline__ int mod_w(int x) {
     return (x + 16 * W) % W;
 }
 
-// The launch covers the tiles of the current layer pass (tile layers
-// pl0 / kTileT onwards); the result is the global tile index.
-__device__ __forceinline__ int tile_of_block(const DevParams& P) {
+// The launch has one block per tile of the current layer pass (tile layers
+// pl0 / kTileT onwards), and the blocks take the pass's occupied tiles from the
+// ordered list (groups of 4 neighbours per XCD); the result is the global tile
+// index, or -1 for a block beyond the occupied tiles (it exits at once).
+__device__ __forceinline__ int tile_of_block(const DevParams& P, const uint32_t* __restrict__ tlist,
+                                             const uint32_t* __restrict__ tpos) {
     const int per_layer = P.nbs * P.nbr;
     const int nbt_pass = (P.pln + kTileT - 1) / kTileT;
-    return (P.pl0 / kTileT) * per_layer + xcd_interleave<4>(blockIdx.x, nbt_pass * per_layer);
+    const int a = (P.pl0 / kTileT) * per_layer, e = a + nbt_pass * per_layer;
+    const int first = int(tpos[a]), cnt = int(tpos[e]) - first;
+    if (int(blockIdx.x) >= cnt) return -1;
+    return int(tlist[first + xcd_interleave<4>(blockIdx.x, cnt)]);
 }
 
 // Kernel weights of one record on the three axes by Horner's rule; the same
@@ -585,7 +600,8 @@ template <typename R, int W>
 __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ rec,
                                                     const uint32_t* __restrict__ start,
                                                     const uint32_t* __restrict__ cls,
-                                                    const uint8_t* __restrict__ occ, DevParams P,
+                                                    const uint32_t* __restrict__ tlist,
+                                                    const uint32_t* __restrict__ tpos, DevParams P,
                                                     const R* __restrict__ coef_g, cpx<R>* __restrict__ stack) {
     using Cfg = ScatterCfg<R, W>;
     constexpr int PI = Cfg::kPI, WB = Cfg::kWaveBatch, D = KernelDegree<R>::value;
@@ -595,8 +611,8 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     __shared__ R coef[W * (D + 1)];
     __shared__ TileSegs sg;
 
-    const int tile = tile_of_block(P);
-    if (!occ[tile]) return;     // no visibility reaches it: left unwritten, read as zero
+    const int tile = tile_of_block(P, tlist, tpos);
+    if (tile < 0) return;     // unoccupied tiles are left unwritten and read as zero
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0 % (P.nbt * kTileT));   // layers of its channel
@@ -789,7 +805,8 @@ template <typename R, int W>
 __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__ rec,
                                                       const uint32_t* __restrict__ start,
                                                       const uint32_t* __restrict__ cls,
-                                                      const uint8_t* __restrict__ occ, DevParams P,
+                                                      const uint32_t* __restrict__ tlist,
+                                                      const uint32_t* __restrict__ tpos, DevParams P,
                                                       const R* __restrict__ coef_g,
                                                       const cpx<R>* __restrict__ stack, cpx<R>* __restrict__ part,
                                                       size_t part_stride) {
@@ -800,8 +817,8 @@ __global__ void __launch_bounds__(256) k_degrid_tiles(const Rec<R>* __restrict__
     __shared__ R coef[W * (D + 1)];
     __shared__ TileSegs sg;
 
-    const int tile = tile_of_block(P);
-    if (!occ[tile]) return;     // no visibility reaches it
+    const int tile = tile_of_block(P, tlist, tpos);
+    if (tile < 0) return;     // only occupied tiles are visited
     const int br = tile % P.nbr, bs = (tile / P.nbr) % P.nbs, bt = tile / (P.nbr * P.nbs);
     const int r0 = br * kTileR, s0 = bs * kTileS, t0 = bt * kTileT;
     const int nt_valid = min(kTileT, P.n_layers - t0 % (P.nbt * kTileT));   // layers of its channel

@@ -97,7 +97,8 @@ struct wsg_plan {
 namespace {
 
 struct Layout {
-    size_t stack, inter, inter2, rec, rec2, part, count, start, cursor, bsums, cls, occ, rows, chan, skipped, total;
+    size_t stack, inter, inter2, rec, rec2, part, count, start, cursor, bsums, cls, occ, rows, chan, tpos, tlist, skipped,
+        total;
     int nch, nbins, nscan;
     int last_layer;    // end of the last channel's layers on the virtual layer axis
     int pass_layers;   // virtual layers held in the stack and FFT buffers at a time (a multiple of kTileT, or all)
@@ -137,6 +138,8 @@ Layout layout_of(const wsg_plan* p, int prec, int64_t M, int tiles_per_pass, int
     L.cls = off;     off += al256(size_t(L.nbins) * 8 * 4);
     L.occ = off;     off += al256(size_t(L.nbins));
     L.rows = off;    off += al256(size_t(nch) * p->nbt * p->nbr);
+    L.tpos = off;    off += al256(size_t(L.nbins + 1) * 4);
+    L.tlist = off;   off += al256(size_t(L.nbins) * 4);
     L.chan = off;    off += al256(sizeof(long long) * (kMaxChannels + 1)) + al256(sizeof(int) * (kMaxChannels + 1));
     // the large buffers start on 2 MiB boundaries (their power-of-two line
     // strides then meet the memory channels the same way whatever precedes them)
@@ -190,23 +193,26 @@ void scan(const uint32_t* count, uint32_t* start, uint32_t* bsums, int n, hipStr
 
 template <typename R, int W>
 void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
-                    const uint8_t* occ, const DevParams& P, const R* coef, cpx<R>* stack, cpx<R>* part,
-                    size_t part_stride, hipStream_t s) {
+                    const uint32_t* tlist, const uint32_t* tpos, const DevParams& P, const R* coef, cpx<R>* stack,
+                    cpx<R>* part, size_t part_stride, hipStream_t s) {
     if (grid)
-        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, occ, P, coef,
-                           stack);
+        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, tlist, tpos, P,
+                           coef, stack);
     else
-        hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, occ, P, coef,
+        hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, tlist, tpos, P,
+                           coef,
                            (const cpx<R>*)stack, part, part_stride);
 }
 
 template <typename R>
 void launch_tiles(bool grid, int W, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
-                  const uint8_t* occ, const DevParams& P, const R* coef, cpx<R>* stack, cpx<R>* part,
-                  size_t part_stride, hipStream_t s) {
+                  const uint32_t* tlist, const uint32_t* tpos, const DevParams& P, const R* coef, cpx<R>* stack,
+                  cpx<R>* part, size_t part_stride, hipStream_t s) {
     switch (W) {
 #define WSG_W(w) \
-    case w: launch_tiles_w<R, w>(grid, nblocks, rec, start, cls, occ, P, coef, stack, part, part_stride, s); break;
+    case w:                                                                                                      \
+        launch_tiles_w<R, w>(grid, nblocks, rec, start, cls, tlist, tpos, P, coef, stack, part, part_stride, s); \
+        break;
         WSG_W(1) WSG_W(2) WSG_W(3) WSG_W(4) WSG_W(5) WSG_W(6) WSG_W(7) WSG_W(8)
         WSG_W(9) WSG_W(10) WSG_W(11) WSG_W(12) WSG_W(13) WSG_W(14) WSG_W(15) WSG_W(16)
 #undef WSG_W
@@ -362,6 +368,8 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
     auto* cls = reinterpret_cast<uint32_t*>(w + L.cls);
     auto* occ = reinterpret_cast<uint8_t*>(w + L.occ);
     auto* rows = reinterpret_cast<uint8_t*>(w + L.rows);
+    auto* tpos = reinterpret_cast<uint32_t*>(w + L.tpos);
+    auto* tlist = reinterpret_cast<uint32_t*>(w + L.tlist);
     auto* coff = reinterpret_cast<long long*>(w + L.chan);
     auto* cblk = reinterpret_cast<int*>(w + L.chan + al256(sizeof(long long) * (kMaxChannels + 1)));
     auto* skipped = reinterpret_cast<uint32_t*>(w + L.skipped);
@@ -400,8 +408,13 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
                                (const uint32_t*)start, cls, P);
         }
         fill<uint8_t>(rows, size_t(L.nch) * P.nbt * P.nbr, uint8_t(0), s);
+        // occupancy marks, then the ordered list of occupied tiles (the bin
+        // counts are no longer needed: they take the 32-bit marks for the scan)
         hipLaunchKernelGGL(k_tile_occupancy, dim3((L.nbins + 255) / 256), dim3(256), 0, s, (const uint32_t*)start,
-                           (const uint32_t*)cls, P, occ, rows);
+                           (const uint32_t*)cls, P, occ, rows, count);
+        scan(count, tpos, bsums, L.nbins, s);
+        hipLaunchKernelGGL(k_tile_list, dim3((L.nbins + 255) / 256), dim3(256), 0, s, (const uint8_t*)occ,
+                           (const uint32_t*)tpos, L.nbins, tlist);
     }
     // Layer passes over the virtual layer axis (channel c's layers start at
     // c nbt kTileT): the stack and FFT buffers hold L.pass_layers layers at a
@@ -420,7 +433,7 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
         if (grid) {
             {
                 StageMark mark(s, 1);
-                launch_tiles<R>(true, P.W, nblocks, rec, start, cls, occ, Q, coef, stack, nullptr, 0, s);
+                launch_tiles<R>(true, P.W, nblocks, rec, start, cls, tlist, tpos, Q, coef, stack, nullptr, 0, s);
             }
             launch_fft<R>(true, plan->log2_np, Q, occ, rows, stack, inter, inter2, tw, corr, nullptr,
                           static_cast<R*>(out), s);
@@ -429,7 +442,8 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
                           static_cast<const R*>(in), nullptr, s);
             if (M > 0) {
                 StageMark mark(s, 7);
-                launch_tiles<R>(false, P.W, nblocks, rec, start, cls, occ, Q, coef, stack, part, size_t(M), s);
+                launch_tiles<R>(false, P.W, nblocks, rec, start, cls, tlist, tpos, Q, coef, stack, part, size_t(M),
+                                s);
             }
         }
     }
