@@ -1014,6 +1014,16 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
     }
 }
 
+// Bit k set when frequency r = j + T k (the k-th value of thread j of a line)
+// lies in a marked row of tiles of the tile layer whose marks start at `mark`.
+template <int T>
+__device__ __forceinline__ uint32_t live_mask(const uint8_t* __restrict__ mark, int j) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m |= uint32_t(mark[(j + T * k) / kTileR] != 0) << k;
+    return m;
+}
+
 // grid pass B: IFFT along r of intermediate rows [t][q][:] for every layer t,
 // w-screen exp(+i 2 pi t z) and accumulation of the real part in registers
 // (Algorithm 5 steps 3b-4), then the 3-D correction (step 5): dirty[q][p].
@@ -1022,8 +1032,8 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
 // channel; `accumulate` adds to the map instead of writing it.
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
-    k_grid_fft_b(const cpx<R>* __restrict__ inter, const cpx<R>* __restrict__ tw, const R* __restrict__ corr,
-                 R* __restrict__ dirty, DevParams P, int seg0, int tloc0, int accumulate) {
+    k_grid_fft_b(const cpx<R>* __restrict__ inter, const uint8_t* __restrict__ rows, const cpx<R>* __restrict__ tw,
+                 const R* __restrict__ corr, R* __restrict__ dirty, DevParams P, int seg0, int tloc0, int accumulate) {
     using C = FftCfg<R, LOGN>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLr, LP = LinePad<Np>::size;
     __shared__ cpx<R> buf[NL * LP];
@@ -1048,11 +1058,20 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         z[k] = nm1 / P.nscale + P.zshift;                     // (n - n0) / n_scale
         acc[k] = R(0);
     }
+    // bit k: frequency r = j + T k lies in a row of tiles with an occupied tile
+    // in the current tile layer (the others are zero and not stored)
+    uint32_t live = 0;
+    int live_layer = -1;
     for (int t = 0; t < P.pln; ++t) {
         const cpx<R>* src = inter + ((size_t)(seg0 + t) * N + qq) * Np;
+        const int tile_layer = __builtin_amdgcn_readfirstlane((P.pl0 + seg0 + t) / kTileT);
+        if (tile_layer != live_layer) {
+            live_layer = tile_layer;
+            live = live_mask<T>(rows + (size_t)tile_layer * P.nbr, j);
+        }
         cpx<R> v[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = src[j + T * k];
+        for (int k = 0; k < 16; ++k) v[k] = (live >> k) & 1u ? src[j + T * k] : cpx<R>{R(0), R(0)};
         fft_line<R, LOGN, +1>(v, lbuf, tw, j);
         const double tl = double(tloc0 + t + P.t_lo);
 #pragma unroll
@@ -1081,7 +1100,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 template <typename R, int LOGN>
 __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
     k_degrid_fft_b(const R* __restrict__ image, const R* __restrict__ corr, const cpx<R>* __restrict__ tw,
-                   cpx<R>* __restrict__ inter, DevParams P, int seg0, int tloc0) {
+                   const uint8_t* __restrict__ rows, cpx<R>* __restrict__ inter, DevParams P, int seg0, int tloc0) {
     using C = FftCfg<R, LOGN>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLr, LP = LinePad<Np>::size;
     __shared__ cpx<R> buf[NL * LP];
@@ -1105,6 +1124,8 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         const double nm1 = -r2 / (1.0 + sqrt(1.0 - r2));
         z[k] = nm1 / P.nscale + P.zshift;
     }
+    uint32_t live = 0;
+    int live_layer = -1;
     for (int t = 0; t < P.pln; ++t) {
         const double tl = double(tloc0 + t + P.t_lo);
         cpx<R> v[16];
@@ -1116,9 +1137,16 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         }
         fft_line<R, LOGN, -1>(v, lbuf, tw, j);
         if (row_ok) {
+            // only frequencies r of rows of tiles with an occupied tile are used later
+            const int tile_layer = __builtin_amdgcn_readfirstlane((P.pl0 + seg0 + t) / kTileT);
+            if (tile_layer != live_layer) {
+                live_layer = tile_layer;
+                live = live_mask<T>(rows + (size_t)tile_layer * P.nbr, j);
+            }
             cpx<R>* dst = inter + ((size_t)(seg0 + t) * N + q) * Np;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) dst[j + T * k] = v[k];
+            for (int k = 0; k < 16; ++k)
+                if ((live >> k) & 1u) dst[j + T * k] = v[k];
         }
     }
 }
@@ -1200,20 +1228,20 @@ __global__ void __launch_bounds__(THREADS) k_transpose(const cpx<R>* __restrict_
     if (threadIdx.x < 4)
         live[threadIdx.x] = rows[((t + t_base) / kTileT) * nbr + min(r0 / kTileR + int(threadIdx.x), nbr - 1)];
     __syncthreads();
-    if (!R_IN && !(live[0] | live[1] | live[2] | live[3])) return;
+    if (!(live[0] | live[1] | live[2] | live[3])) return;
+    // only the live frequencies r are moved: the others are zero in the grid
+    // direction (the pass-B FFT reads them as zeros) and unused in the degrid
+    // direction (pass A' skips their rows)
     const cpx<R>* src = in + (size_t)t * A * B;
     for (int i = threadIdx.x; i < 64 * 64; i += THREADS) {
         const int a = a0 + i / 64, b = b0 + i % 64;
-        if (a < A && b < B) {
-            const bool on = !R_IN || live[(i / 64) / kTileR];
-            tile[i / 64][i % 64] = on ? src[(size_t)a * B + b] : cpx<R>{R(0), R(0)};
-        }
+        if (a < A && b < B && live[(R_IN ? i / 64 : i % 64) / kTileR]) tile[i / 64][i % 64] = src[(size_t)a * B + b];
     }
     __syncthreads();
     cpx<R>* dst = out + (size_t)t * A * B;
     for (int i = threadIdx.x; i < 64 * 64; i += THREADS) {
         const int b = b0 + i / 64, a = a0 + i % 64;
-        if (a < A && b < B && (R_IN || live[(i / 64) / kTileR])) dst[(size_t)b * A + a] = tile[i % 64][i / 64];
+        if (a < A && b < B && live[(R_IN ? i % 64 : i / 64) / kTileR]) dst[(size_t)b * A + a] = tile[i % 64][i / 64];
     }
 }
 

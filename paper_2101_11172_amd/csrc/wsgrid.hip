@@ -271,8 +271,8 @@ void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, const uint8
             DevParams Q = P;
             Q.pln = hi - lo;
             hipLaunchKernelGGL((k_grid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
-                               (const cpx<R>*)inter2, tw, corr, dirty + size_t(c) * map, Q, lo - P.pl0, lo - c * chl,
-                               lo > c * chl ? 1 : 0);
+                               (const cpx<R>*)inter2, rows, tw, corr, dirty + size_t(c) * map, Q, lo - P.pl0,
+                               lo - c * chl, lo > c * chl ? 1 : 0);
         });
     } else {
         {
@@ -281,7 +281,7 @@ void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, const uint8
                 DevParams Q = P;
                 Q.pln = hi - lo;
                 hipLaunchKernelGGL((k_degrid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
-                                   image + size_t(c) * map, corr, tw, inter, Q, lo - P.pl0, lo - c * chl);
+                                   image + size_t(c) * map, corr, tw, rows, inter, Q, lo - P.pl0, lo - c * chl);
             });
         }
         {
