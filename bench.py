@@ -81,7 +81,6 @@ def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict) 
     b = 16 if f64 else 8            # complex
     r = 8 if f64 else 4             # real
     rec = 56 if f64 else 32         # binned record
-    inter = nl * N * Np * b
     tiles = ws["occupied_cells"] * b                    # occupied tiles of the stack
     inter_rows = ws["nonempty_lines"] * N * b           # intermediate lines that meet an occupied tile
     sort = 2 * M * rec                                  # per-bin sort: records in and out
@@ -89,11 +88,11 @@ def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict) 
         "grid_bin": M * (2 * 24 + b + rec) + sort,      # uvw read twice, vis, records written, sorted
         "grid_tiles": ws["tile_visits"] * rec + tiles,  # records in (once per tile reached), tiles out
         "grid_fft_v": tiles + inter_rows,               # occupied tiles in, lines of occupied rows out
-        "grid_transpose": inter_rows + inter,           # those lines in (the others are zero), all out
+        "grid_transpose": inter_rows + inter_rows,      # live lines in and out (the others are zero)
         "degrid_transpose": inter_rows + inter_rows,    # lines the transform along q needs, in and out
-        "grid_fft_u": inter + 2 * N * N * r,            # intermediate, correction in, map out
+        "grid_fft_u": inter_rows + 2 * N * N * r,       # live intermediate, correction in, map out
         "degrid_bin": M * (2 * 24 + rec) + sort,
-        "degrid_fft_p": 2 * N * N * r + inter,          # image, correction in, intermediate out
+        "degrid_fft_p": 2 * N * N * r + inter_rows,     # image, correction in, live intermediate out
         "degrid_fft_q": inter_rows + tiles,             # intermediate rows in, occupied tiles out
         # tiles and records in, one part out per visit; then per record its parts in, the visibility out
         "degrid_tiles": tiles + ws["tile_visits"] * (rec + b) + M * rec + ws["tile_visits"] * b + M * b,
