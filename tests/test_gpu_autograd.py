@@ -20,7 +20,7 @@ from paper_2101_11172_amd import wsgrid as wg
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda", 0)
-N, L, W, x0, wmax, M = 64, 0.3, 7, 0.25, 100.0, 900
+N, L, W, x0, wmax, M = 256, 0.3, 7, 0.25, 100.0, 3000    # a 256^2 sub-problem of the imaging workload
 
 
 @pytest.fixture(scope="module")
@@ -74,7 +74,8 @@ def test_gradient_finite_differences(problem):
         e = e.reshape(N, N)
         fd = (L_of(f + e) - L_of(f - e)) / (2 * h)      # exact for a quadratic up to rounding
         gp = g.ravel()[p]
-        assert abs(fd - gp) <= 1e-6 * max(1.0, abs(gp)) + 1e-9 * L_of(f) / h, (p, fd, gp)
+        # FP64 rounding of L is ~1e-15 L; allow 1e-12 L / h for the difference of two
+        assert abs(fd - gp) <= 1e-6 * max(1.0, abs(gp)) + 1e-12 * L_of(f) / h, (p, fd, gp)
 
 
 def test_least_squares_steps_decrease_the_loss(problem):
