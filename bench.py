@@ -510,6 +510,9 @@ def main() -> int:
         "fp64": fp64,
         "fp32_vs_fp64_rel_rms": acc,
         "stages": tab32,
+        # each call separately: the sum of its stage times (HIP events, FP32)
+        "stage_sum_ms_per_call": {c: sum(v["ms"] for k, v in tab32.items() if k.startswith(c + "_"))
+                                  for c in ("grid", "degrid")},
         "stack_occupancy": ws,
         "skipped": skipped,
     }
