@@ -25,9 +25,16 @@
  *     is skipped: grid ignores it, degrid returns 0 for it.
  *   - vis: M complex values, interleaved (re, im): complex64 for WSG_F32,
  *     complex128 for WSG_F64.  Image/dirty: float32 for WSG_F32, float64 for WSG_F64.
- *   - all array pointers given to grid_visibilities / degrid_visibilities are
- *     HIP device pointers owned by the caller; the call only enqueues work on
- *     `stream` (a hipStream_t, NULL = default stream) and returns.
+ *   - all array pointers given to grid_visibilities / degrid_visibilities (and
+ *     their _batch forms) are HIP device pointers owned by the caller; the call
+ *     only enqueues work on `stream` (a hipStream_t, NULL = default stream) and
+ *     returns.  Host memory is used only for the plan, the channel counts of a
+ *     batched call and the error message; the library allocates device memory
+ *     only in grid_create (its tables).
+ *   - memory: the caller's workspace holds the binned visibilities, the layer
+ *     stack and the FFT intermediates; a workspace smaller than the one that
+ *     holds every layer makes the call take the layers in passes of whole tile
+ *     layers (16 w-layers), with the same results.
  *   - return value 0 on success, or a negative WSG_E* code; the message is in
  *     grid_last_error() (thread-local).
  */
