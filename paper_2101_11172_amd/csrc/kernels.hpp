@@ -444,7 +444,7 @@ struct KernelDegree {
 struct TileSegs {
     uint32_t lo[64];
     uint32_t off[65];
-    uint32_t nbr[64];     // neighbour set of the range's bin: it | ir << 1 | is << 2
+    uint8_t nbr[64];      // neighbour set of the range's bin: it | ir << 1 | is << 2
     int n;
 };
 
@@ -482,7 +482,7 @@ __device__ __forceinline__ void tile_segments(const uint32_t* __restrict__ start
         const int g = __popcll(fm & ((1ull << lane) - 1ull));
         sg.lo[g] = lo;
         sg.off[g] = inc - len;
-        sg.nbr[g] = uint32_t(it | (ir << 1) | (is << 2));
+        sg.nbr[g] = uint8_t(it | (ir << 1) | (is << 2));
     }
     if (lane == 63) {
         const int n = __popcll(fm);
@@ -568,8 +568,8 @@ __device__ __forceinline__ int word_bits(double v) { return __double2loint(v); }
 // v indices are congruent to x and y modulo W, one per layer residue a: for
 // support start (dr, ds, dt) the u-cell dr + ((x - dr) mod W), the v-cell
 // ds + ((y - ds) mod W) and the layer dt + ((a - dt) mod W).  Each round a wave
-// stages 32 records into its slots (two lanes per record): the u weights times the value
-// and the v weights rotated by the support start (so lane x reads position x
+// stages 16 or 32 records into its slots (four or two lanes per record): the u
+// weights times the value and the v weights rotated by the support start (so lane x reads position x
 // whatever the record), and the layer weights rotated by dt with the packed
 // support start, read by the whole wave as broadcasts.  Sums stay in registers
 // while the owned cell stays the same; when the support moves, the lanes (or
@@ -579,7 +579,11 @@ __device__ __forceinline__ int word_bits(double v) { return __double2loint(v); }
 // move by one cell.
 template <typename R, int W>
 struct ScatterCfg {
-    static constexpr int kWaveBatch = 32;      // records per wave round (small stage: 3 blocks per CU)
+    // records per wave round: 16 (four lanes stage each) where the block then
+    // fits in 40 KB of LDS and four blocks share a CU (FP32, W <= 7), else 32
+    // (two lanes each; three blocks per CU)
+    static constexpr int kWaveBatch = (sizeof(R) == 4 && W <= 7) ? 16 : 32;
+    static constexpr int kLanesPerRecord = 64 / kWaveBatch;
     static constexpr int kSlots = 4 * kWaveBatch;
     static constexpr int kPairs = W * W;
     static constexpr int kPI = (kPairs + 63) / 64;                // (x, y) residue pairs per lane
@@ -608,7 +612,6 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     __shared__ R tre[Cfg::kCells];
     __shared__ R tim[Cfg::kCells];
     __shared__ ScatterStage<R, W> st;
-    __shared__ R coef[W * (D + 1)];
     __shared__ TileSegs sg;
 
     const int tile = tile_of_block(P, tlist, tpos);
@@ -621,7 +624,6 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
 
     if (tid < 64) tile_segments(start, cls, P, bt, bs, br, sg);
     for (int i = tid; i < Cfg::kCells; i += 256) tre[i] = tim[i] = R(0);
-    for (int i = tid; i < W * (D + 1); i += 256) coef[i] = coef_g[i];
     __syncthreads();
     const int nseg = sg.n;
     const uint32_t total = sg.off[nseg];
@@ -698,11 +700,13 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
         };
 
         const int slot0 = wv * WB;
-        // staging: lanes rl and rl + 32 take record rl, the first the kernel
-        // segments [0, A0), the second [A0, W), so the Horner work is spread
-        // over the whole wave
-        static_assert(2 * WB == 64, "two lanes per staged record");
-        constexpr int A0 = (W + 1) / 2;
+        // staging: the lanes rl + WB h (h = 0 .. LPR - 1) take record rl, lane h
+        // the kernel segments [h A0, (h + 1) A0), so the Horner work is spread
+        // over the whole wave; the coefficients come from global memory (the
+        // whole wave reads the same few, so the vector cache serves them)
+        constexpr int LPR = Cfg::kLanesPerRecord;
+        static_assert(WB * LPR == 64, "the wave stages WB records with LPR lanes each");
+        constexpr int A0 = (W + LPR - 1) / LPR;
         const int rl = lane & (WB - 1), half = lane / WB;
         Rec<R> nxt;
         if (q0 + uint32_t(rl) < q1) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(rl))];
@@ -718,7 +722,7 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
 #pragma unroll
                 for (int i = 0; i < A0; ++i) {
                     const int a = i + half * A0;
-                    const R* c = coef + min(a, W - 1) * (D + 1);
+                    const R* c = coef_g + min(a, W - 1) * (D + 1);
                     R hu = c[D], hv = c[D], ht = c[D];
 #pragma unroll
                     for (int k = D - 1; k >= 0; --k) {
