@@ -579,10 +579,10 @@ __device__ __forceinline__ int word_bits(double v) { return __double2loint(v); }
 // move by one cell.
 template <typename R, int W>
 struct ScatterCfg {
-    // records per wave round: 16 (four lanes stage each) where the block then
-    // fits in 40 KB of LDS and four blocks share a CU (FP32, W <= 7), else 32
-    // (two lanes each; three blocks per CU)
-    static constexpr int kWaveBatch = (sizeof(R) == 4 && W <= 7) ? 16 : 32;
+    // records per wave round: 16 (four lanes stage each) for W <= 7, where the
+    // block then fits in 40 KB of LDS (FP32: four blocks per CU) or 80 KB
+    // (FP64: two), else 32 (two lanes each)
+    static constexpr int kWaveBatch = W <= 7 ? 16 : 32;
     static constexpr int kLanesPerRecord = 64 / kWaveBatch;
     static constexpr int kSlots = 4 * kWaveBatch;
     static constexpr int kPairs = W * W;
