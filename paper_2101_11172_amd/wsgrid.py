@@ -266,7 +266,9 @@ class Plan:
         if self.max_workspace_bytes is not None and need > self.max_workspace_bytes:
             need = max(grid_workspace_bytes_batch(self._p, prec, nch, M, True), int(self.max_workspace_bytes))
         ws = self._ws.get(prec)
-        if ws is None or ws.numel() < need:
+        over_cap = (ws is not None and self.max_workspace_bytes is not None
+                    and ws.numel() > max(need, int(self.max_workspace_bytes)))
+        if ws is None or ws.numel() < need or over_cap:
             self._ws.pop(prec, None)
             ws = torch.empty(need, dtype=torch.uint8, device=self.device)
             self._ws[prec] = ws

@@ -291,3 +291,20 @@ def test_no_offset_variant(case):
         assert rel(g, ref_g) <= tol, (prec, "grid", rel(g, ref_g))
         assert rel(d, ref_d) <= tol, (prec, "degrid", rel(d, ref_d))
     plan.close()
+
+
+def test_lowering_the_cap_shrinks_the_workspace():
+    """A Plan whose max_workspace_bytes is lowered after a call allocates the
+    smaller workspace on the next call (and the result does not change)."""
+    N, L, W, x0, wmax, M = 128, 0.8, 7, 0.25, 300.0, 500
+    plan = wg.Plan(N, L, W, x0, wmax, device=DEV)
+    uvw = torch.from_numpy(inputs.uniform_uvw(M, 0.9 * N / (2 * L), wmax, 5)).to(DEV)
+    vis = torch.from_numpy(inputs.random_vis(M, 6)).to(DEV)
+    g_full = plan.grid(uvw, vis).cpu().numpy()
+    assert plan.workspace(wg.WSG_F64, M).numel() == wg.grid_workspace_bytes(plan._p, wg.WSG_F64, M)
+    least = wg.grid_workspace_bytes_min(plan._p, wg.WSG_F64, M)
+    plan.max_workspace_bytes = least
+    g_small = plan.grid(uvw, vis).cpu().numpy()
+    assert plan.workspace(wg.WSG_F64, M).numel() == least
+    assert rel(g_small, g_full) <= 1e-14
+    plan.close()
