@@ -52,7 +52,6 @@ def workload_stats(uvw, N: int, L: float, W: int, x0: float, wmax: float, Np: in
     ft = np.floor(n_scale * w + W / 2).astype(np.int64) - W + 1 - t_lo
     T = 16
     nb, nbt = Np // T, (nl + T - 1) // T
-    cnt = np.bincount((ft // T * nb + fv // T) * nb + fu // T, minlength=nbt * nb * nb).reshape(nbt, nb, nb)
     B = 17 - W
     ct, cv, cu = ft % T >= B, fv % T >= B, fu % T >= B
     visits = int(np.sum((1 + ct) * (1 + cu) * (1 + cv)))
