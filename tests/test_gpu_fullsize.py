@@ -2,16 +2,17 @@
 W = 7, x0 = 0.25, 9,999,360 visibilities, 49 layers; and the low-cost W = 4,
 x0 = 1/2 setting on the same geometry), same plan and launches as bench.py.
 
-The FP64 oracle cannot run at this size, so the checks are properties that hold
-at any size:
+The oracle's element-wise comparison at this geometry (all 49 layers, N' =
+4096, on a subsample of the tracks) is tests/test_gpu_oracle_sizes.py.  Here,
+on all 9,999,360 visibilities, the checks are properties that hold at any size:
 * exact DFT (eq. fourier_visibility) at sampled outputs, computed one by one on
   the CPU: the dirty map at 48 random pixels (each a sum over all visibilities)
   and the model visibilities of a 500-source sky at 20,000 random baselines;
   and the dirty map at 10,000 random pixels with the same formula evaluated
   by plain torch float64 operations on the device (pinned to the CPU values
   at 8 of the pixels);
-  bound: the method's sqrt(3) E (Sec. 6.3) with a factor 2, plus the FP32 target
-  1e-6 for the single-precision path;
+  bound: the method's sqrt(3) E (Sec. 6.3) with a factor 2 for FP64, and the
+  single-precision target 1e-6 for FP32 at W = 7, x0 = 1/4;
 * the adjoint identity Re <degrid f, V> = <f, grid V> in FP64 (Sec. 3.1-3.2);
 * FP32 against FP64 on the full arrays (spec target 1e-6 at W = 7).
 """
@@ -21,7 +22,7 @@ import torch
 
 from oracle import dft
 from oracle.plan import make_plan
-from paper_2101_11172_amd import inputs
+from paper_2101_11172_amd import direct, inputs
 from paper_2101_11172_amd import wsgrid as wg
 
 pytestmark = pytest.mark.gpu
@@ -55,12 +56,11 @@ def test_widefield_grid_against_dft(widefield):
     rng = np.random.default_rng(7)
     rows, cols = rng.integers(0, w["N"], 48), rng.integers(0, w["N"], 48)
     exact = dft.dft_grid(w["oplan"], w["uvw"], w["vis"], rows=rows, cols=cols, chunk=8)
-    bound = 2 * np.sqrt(3) * plan.info["E"]
-    for cdt, extra in ((torch.complex128, 0.0), (torch.complex64, 1e-6)):
+    for cdt, bound in ((torch.complex128, 2 * np.sqrt(3) * plan.info["E"]), (torch.complex64, 1e-6)):
         g = plan.grid(w["t_uvw"], torch.from_numpy(w["vis"]).to(DEV, cdt)).cpu().double().numpy()
         e = rel(g[rows, cols], exact)
-        print(f"grid {cdt}: rel err vs DFT at 48 pixels {e:.3e} (bound {bound + extra:.3e})")
-        assert e <= bound + extra
+        print(f"grid {cdt}: rel err vs DFT at 48 pixels {e:.3e} (bound {bound:.3e})")
+        assert e <= bound
 
 
 def test_widefield_degrid_against_dft(widefield):
@@ -68,12 +68,11 @@ def test_widefield_degrid_against_dft(widefield):
     sky = inputs.random_sky(w["N"], 500, 9)
     idx = np.random.default_rng(8).choice(w["uvw"].shape[0], 20000, replace=False)
     exact = dft.dft_degrid(w["oplan"], w["uvw"], sky, vis_index=idx)
-    bound = 2 * np.sqrt(3) * plan.info["E"]
-    for rdt, extra in ((torch.float64, 0.0), (torch.float32, 1e-6)):
+    for rdt, bound in ((torch.float64, 2 * np.sqrt(3) * plan.info["E"]), (torch.float32, 1e-6)):
         v = plan.degrid(w["t_uvw"], torch.from_numpy(sky).to(DEV, rdt)).cpu().to(torch.complex128).numpy()
         e = rel(v[idx], exact)
-        print(f"degrid {rdt}: rel err vs DFT at 20k visibilities {e:.3e} (bound {bound + extra:.3e})")
-        assert e <= bound + extra
+        print(f"degrid {rdt}: rel err vs DFT at 20k visibilities {e:.3e} (bound {bound:.3e})")
+        assert e <= bound
 
 
 def test_widefield_adjoint_fp64(widefield):
@@ -101,28 +100,55 @@ def test_widefield_fp32_against_fp64(widefield):
 
 
 def test_lowcost_against_dft_and_fp64():
+    """Low-cost setting (W = 4, x0 = 1/2, N' = N = 2048): degrid at 10,000
+    sampled visibilities and the dirty map at 10,000 sampled pixels against the
+    direct transform (the method's own error E = 0.07 dominates, so the bound
+    is 2 sqrt(3) E for both precisions), and FP32 against FP64 on the whole
+    outputs: grid compared before the correction h_x h_y h_z (which spans six
+    decades at x0 = 1/2) within 1e-5, degrid within max(1e-6, 2^-24 rms(h h h)).
+    The grid bound is ten times the small-case parity bound: each occupied cell
+    here sums ~100 times more records in float32 (measured 1.4e-6 on all 10M
+    visibilities, 1e-6 or less on 100k), and it stays 7,000 times below the
+    method's own error E(4, 1/2) = 0.07, which the single-precision path then
+    does not change measurably (the 1e-6 target is that of W = 7, x0 = 1/4)."""
     w = inputs.workload("lowcost", vis_dtype=np.complex128)
     plan = wg.Plan(w["N"], w["L"], w["W"], w["x0"], w["wmax"], device=DEV)
     assert plan.info["Nprime"] == 2048
     t_uvw = torch.from_numpy(w["uvw"]).to(DEV)
     op = make_plan(w["N"], w["L"], w["W"], w["x0"], w["wmax"])
+    bound = 2 * np.sqrt(3) * plan.info["E"]
     sky = inputs.random_sky(w["N"], 500, 9)
     idx = np.random.default_rng(8).choice(w["uvw"].shape[0], 10000, replace=False)
     exact = dft.dft_degrid(op, w["uvw"], sky, vis_index=idx)
     v64 = plan.degrid(t_uvw, torch.from_numpy(sky).to(DEV)).cpu().numpy()
     v32 = plan.degrid(t_uvw, torch.from_numpy(sky).to(DEV, torch.float32)).cpu().to(torch.complex128).numpy()
     e64, e32 = rel(v64[idx], exact), rel(v32[idx], exact)
-    print(f"lowcost degrid vs DFT: fp64 {e64:.3e} fp32 {e32:.3e}, E = {plan.info['E']:.3e}")
-    assert e64 <= 2 * np.sqrt(3) * plan.info["E"] and abs(e32 - e64) <= 1e-4
-    # the dirty map at 16 sampled pixels
+    print(f"lowcost degrid vs DFT at 10k visibilities: fp64 {e64:.3e} fp32 {e32:.3e}, E = {plan.info['E']:.3e}")
+    assert e64 <= bound and e32 <= bound
+    # the dirty map at 10,000 sampled pixels (direct transform on the device)
     rng = np.random.default_rng(10)
-    rows, cols = rng.integers(0, w["N"], 16), rng.integers(0, w["N"], 16)
-    exact_g = dft.dft_grid(op, w["uvw"], w["vis"], rows=rows, cols=cols, chunk=8)
-    g64 = plan.grid(t_uvw, torch.from_numpy(w["vis"]).to(DEV)).cpu().numpy()
-    g32 = plan.grid(t_uvw, torch.from_numpy(w["vis"]).to(DEV, torch.complex64)).cpu().double().numpy()
+    rows, cols = rng.integers(0, w["N"], 10000), rng.integers(0, w["N"], 10000)
+    V = torch.from_numpy(w["vis"]).to(DEV)
+    exact_g = direct.dft_grid(t_uvw, V, w["N"], w["L"], rows, cols, progress=True).cpu().numpy()
+    ref8 = dft.dft_grid(op, w["uvw"], w["vis"], rows=rows[:8], cols=cols[:8], chunk=8)
+    assert np.linalg.norm(exact_g[:8] - ref8) <= 1e-9 * np.linalg.norm(ref8)
+    g64 = plan.grid(t_uvw, V).cpu().numpy()
+    g32 = plan.grid(t_uvw, V.to(torch.complex64)).cpu().double().numpy()
     f64, f32 = rel(g64[rows, cols], exact_g), rel(g32[rows, cols], exact_g)
-    print(f"lowcost grid vs DFT at 16 pixels: fp64 {f64:.3e} fp32 {f32:.3e}")
-    assert f64 <= 2 * np.sqrt(3) * plan.info["E"] and abs(f32 - f64) <= 1e-4
+    print(f"lowcost grid vs DFT at 10k pixels: fp64 {f64:.3e} fp32 {f32:.3e}")
+    assert f64 <= bound and f32 <= bound
+    # FP32 against FP64 directly, whole outputs
+    from oracle.kernel_design import least_misfit
+    from oracle.wstack import correction
+    corr = correction(op, least_misfit(w["W"], w["x0"]))
+    eg = rel(g32 / corr, g64 / corr)
+    tol_d = max(1e-6, 2.0 ** -24 * float(np.sqrt(np.mean(corr ** 2))))
+    img = inputs.random_image(w["N"], 14)
+    d64 = plan.degrid(t_uvw, torch.from_numpy(img).to(DEV)).cpu().numpy()
+    d32 = plan.degrid(t_uvw, torch.from_numpy(img).to(DEV, torch.float32)).cpu().to(torch.complex128).numpy()
+    ed = rel(d32, d64)
+    print(f"lowcost fp32 vs fp64: grid before correction {eg:.3e}, degrid {ed:.3e} (bound {tol_d:.2e})")
+    assert eg <= 1e-5 and ed <= tol_d
     plan.close()
 
 
@@ -136,37 +162,12 @@ def test_widefield_no_offset_variant_against_dft(widefield):
     sky = inputs.random_sky(w["N"], 500, 9)
     idx = np.random.default_rng(8).choice(w["uvw"].shape[0], 20000, replace=False)
     exact = dft.dft_degrid(w["oplan"], w["uvw"], sky, vis_index=idx)
-    bound = 2 * np.sqrt(3) * plan.info["E"]
-    for rdt, extra in ((torch.float64, 0.0), (torch.float32, 1e-6)):
+    for rdt, bound in ((torch.float64, 2 * np.sqrt(3) * plan.info["E"]), (torch.float32, 1e-6)):
         v = plan.degrid(w["t_uvw"], torch.from_numpy(sky).to(DEV, rdt)).cpu().to(torch.complex128).numpy()
         e = rel(v[idx], exact)
         print(f"no-offset degrid {rdt}: rel err vs DFT at 20k visibilities {e:.3e} ({plan.info['n_layers']} layers)")
-        assert e <= bound + extra
+        assert e <= bound
     plan.close()
-
-
-def torch_dft_grid(uvw: torch.Tensor, vis: torch.Tensor, N: int, L: float, rows, cols, chunk: int = 16):
-    """D_ji = Re sum_k V_k exp[+i 2 pi (u_k l_i + v_k m_j + w_k (n_ji - 1))] at the
-    listed pixels, with plain torch float64 operations (the definition the
-    method approximates; the same formula as the oracle's dft_grid).  Phases
-    are laid out [pixel][visibility] so that the sum runs along contiguous
-    memory."""
-    dl = L / N
-    u, v, w = (uvw[:, i].contiguous() for i in range(3))
-    vr, vi = vis.real.contiguous(), vis.imag.contiguous()
-    out = []
-    for lo in range(0, len(rows), chunk):
-        l = (torch.as_tensor(cols[lo:lo + chunk], dtype=torch.float64, device=uvw.device) - N // 2) * dl
-        m = (torch.as_tensor(rows[lo:lo + chunk], dtype=torch.float64, device=uvw.device) - N // 2) * dl
-        r2 = l * l + m * m
-        nm1 = -r2 / (1.0 + torch.sqrt(1.0 - r2))
-        ph = l[:, None] * u[None, :] + m[:, None] * v[None, :] + nm1[:, None] * w[None, :]
-        ph = 2.0 * np.pi * (ph - torch.round(ph))
-        out.append(torch.sum(torch.cos(ph) * vr[None, :] - torch.sin(ph) * vi[None, :], dim=1))
-        if (lo // chunk) % 125 == 124:
-            torch.cuda.synchronize()
-            print(f"  direct transform: {lo + chunk} of {len(rows)} pixels", flush=True)
-    return torch.cat(out)
 
 
 def test_widefield_grid_against_dft_10k_pixels(widefield):
@@ -177,12 +178,11 @@ def test_widefield_grid_against_dft_10k_pixels(widefield):
     rng = np.random.default_rng(17)
     rows, cols = rng.integers(0, w["N"], 10000), rng.integers(0, w["N"], 10000)
     V = torch.from_numpy(w["vis"]).to(DEV)
-    exact = torch_dft_grid(w["t_uvw"], V, w["N"], w["L"], rows, cols).cpu().numpy()
+    exact = direct.dft_grid(w["t_uvw"], V, w["N"], w["L"], rows, cols, progress=True).cpu().numpy()
     ref8 = dft.dft_grid(w["oplan"], w["uvw"], w["vis"], rows=rows[:8], cols=cols[:8], chunk=8)
     assert np.linalg.norm(exact[:8] - ref8) <= 1e-9 * np.linalg.norm(ref8)
-    bound = 2 * np.sqrt(3) * plan.info["E"]
-    for cdt, extra in ((torch.complex128, 0.0), (torch.complex64, 1e-6)):
+    for cdt, bound in ((torch.complex128, 2 * np.sqrt(3) * plan.info["E"]), (torch.complex64, 1e-6)):
         g = plan.grid(w["t_uvw"], V.to(cdt)).cpu().double().numpy()
         e = rel(g[rows, cols], exact)
-        print(f"grid {cdt}: rel err vs DFT at 10k pixels {e:.3e} (bound {bound + extra:.3e})")
-        assert e <= bound + extra
+        print(f"grid {cdt}: rel err vs DFT at 10k pixels {e:.3e} (bound {bound:.3e})")
+        assert e <= bound
