@@ -8,7 +8,10 @@ Test infrastructure: see ``oracle/__init__.py``.
   x_i = (i - N/2) / N' with FFT length N' = N / (2 x0) (Algorithm 1: N = 2 x0 N').
 * z = (n - n0) / n_scale on the sphere (eq. z-on-sphere), with
   n_scale = (1 - n_min) / (2 z0) and n0 = 1 - z0 n_scale (eq. n_params),
-  n_min = sqrt(1 - l_max^2 - m_max^2), and z0 = x0 (Sec. 6.2 recommendation).
+  n_min = sqrt(1 - l_max^2 - m_max^2), and z0 = x0 by default (Sec. 6.2
+  recommendation; Sec. 5.2 allows a z-axis gridding function of its own width
+  W_z and cropping z0, eq. gridded_vis with C_z, and Sec. 6.1 trades W_z
+  against z0).
   Then z runs from -z0 (map corners) to +z0 (centre).  The variant without z
   offset (Sec. 5.3, eq. n_params_no_offset) takes n_scale = (1 - n_min) / z0
   and n0 = 1, so that z runs from -z0 to 0 and z = 0 at the map centre, at
@@ -48,14 +51,20 @@ class Plan:
     t_lo: int
     t_hi: int
     z_offset: bool = True
+    Wz: int = 0            # width of C_z (0: the same as W)
+    z0v: float = 0.0       # z cropping z0 (0: the same as x0)
 
     @property
     def n_layers(self) -> int:
         return self.t_hi - self.t_lo + 1
 
     @property
+    def W_z(self) -> int:
+        return self.Wz or self.W
+
+    @property
     def z0(self) -> float:
-        return self.x0
+        return self.z0v or self.x0
 
     @property
     def z_shift(self) -> float:
@@ -84,7 +93,10 @@ class Plan:
         return self.n_minus_1() / self.n_scale + self.z_shift
 
 
-def make_plan(N: int, L: float, W: int, x0: float, wmax: float, z_offset: bool = True) -> Plan:
+def make_plan(N: int, L: float, W: int, x0: float, wmax: float, z_offset: bool = True,
+              Wz: int | None = None, z0: float | None = None) -> Plan:
+    """Plan of the improved method; Wz, z0 default to W, x0 (the same gridding
+    function on all three axes)."""
     if N <= 0 or N % 2:
         raise ValueError("N must be positive and even")
     if not (0.0 < x0 <= 0.5):
@@ -92,25 +104,29 @@ def make_plan(N: int, L: float, W: int, x0: float, wmax: float, z_offset: bool =
     Np = N / (2.0 * x0)
     if abs(Np - round(Np)) > 1e-9:
         raise ValueError("N / (2 x0) must be an integer")
-    if not (1 <= W <= 16):
-        raise ValueError("W must be in [1, 16]")
+    Wz = W if Wz is None else int(Wz)
+    z0 = x0 if z0 is None else float(z0)
+    if not (1 <= W <= 16) or not (1 <= Wz <= 16):
+        raise ValueError("W and W_z must be in [1, 16]")
+    if not (0.0 < z0 <= 0.5):
+        raise ValueError("z0 must be in (0, 1/2]")
     if not (0.0 < L < math.sqrt(2.0)):
         raise ValueError("L must be in (0, sqrt 2)")
     if not (wmax >= 0.0):
         raise ValueError("wmax must be >= 0")
     l_max = 0.5 * L
     n_min = math.sqrt(1.0 - 2.0 * l_max * l_max)
-    z0 = x0
     if z_offset:
         n_scale = (1.0 - n_min) / (2.0 * z0)      # eq. n_params
         n0 = 1.0 - z0 * n_scale
     else:
         n_scale = (1.0 - n_min) / z0              # eq. n_params_no_offset
         n0 = 1.0
-    t_lo = W // 2 - W + 1
-    t_hi = int(math.floor(n_scale * wmax + 0.5 * W))
+    t_lo = Wz // 2 - Wz + 1
+    t_hi = int(math.floor(n_scale * wmax + 0.5 * Wz))
     return Plan(N=N, L=L, W=W, x0=x0, wmax=wmax, Nprime=int(round(Np)), l_max=l_max,
-                n_min=n_min, n_scale=n_scale, n0=n0, t_lo=t_lo, t_hi=t_hi, z_offset=z_offset)
+                n_min=n_min, n_scale=n_scale, n0=n0, t_lo=t_lo, t_hi=t_hi, z_offset=z_offset,
+                Wz=Wz, z0v=z0)
 
 
 def layers_required(dn_dw: float, z0: float, W: int) -> int:

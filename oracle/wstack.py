@@ -12,8 +12,9 @@ Conventions (readings listed in the design doc):
   s_a = a - (W-1)/2;
 * uv-grid points are indexed modulo N' (the FFT is periodic in r, s), w-layers by
   t - t_lo;
-* all transforms are unnormalised; dirty map uses e^{+i}, visibilities e^{-i}
-  (eq. fourier_visibility); no natural weights 1/M; the image is f = I/n;
+* all transforms are unnormalised (scipy.fft on every core); dirty map uses
+  e^{+i}, visibilities e^{-i} (eq. fourier_visibility); no natural weights 1/M;
+  the image is f = I/n;
 * Hermitian fold (Sec. 5.4): a visibility with w < 0 is replaced by its conjugate
   at (-u, -v, -w); visibilities with |w| > w_max are skipped (degrid returns 0).
 
@@ -24,10 +25,17 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
+import os
+
 import numpy as np
+import scipy.fft
 
 from .kernel_design import LeastMisfit
 from .plan import Plan
+
+
+# threads for the library 2-D transforms (the only multi-threaded step)
+_WORKERS = os.cpu_count() or 1
 
 
 def support(xi: np.ndarray, W: int):
@@ -56,11 +64,24 @@ def _weights(lm: LeastMisfit, xi: np.ndarray, W: int):
     return first, lm.c(nu)                      # [M], [M, W]
 
 
+_CORRECTIONS: dict = {}
+
+
 def correction(plan: Plan, lm: LeastMisfit) -> np.ndarray:
-    """h_x(x) h_y(y) h_z(z(x, y)) on the [j, i] pixel grid (Algorithm 5 step 5)."""
-    hx = lm.h(plan.pixel_x())
-    hz = lm.h(plan.z().ravel()).reshape(plan.N, plan.N)
-    return hx[None, :] * hx[:, None] * hz
+    """h_x(x) h_y(y) h_z(z(x, y)) on the [j, i] pixel grid (Algorithm 5 step 5).
+
+    The map depends only on the plan and the design, so the last few are kept
+    (read-only) for the next grid or degrid call."""
+    key = (plan, id(lm))
+    if key not in _CORRECTIONS:
+        hx = lm.h(plan.pixel_x())
+        hz = lm.h(plan.z().ravel()).reshape(plan.N, plan.N)
+        c = hx[None, :] * hx[:, None] * hz
+        c.setflags(write=False)
+        if len(_CORRECTIONS) >= 4:
+            _CORRECTIONS.pop(next(iter(_CORRECTIONS)))
+        _CORRECTIONS[key] = (lm, c)
+    return _CORRECTIONS[key][1]
 
 
 def _crop(plan: Plan) -> np.ndarray:
@@ -82,10 +103,11 @@ class GridInput:
     cy: np.ndarray
 
 
-def grid_prepare(plan: Plan, lm: LeastMisfit, uvw, vis) -> GridInput:
+def grid_prepare(plan: Plan, lm: LeastMisfit, uvw, vis, lmz: LeastMisfit | None = None) -> GridInput:
     """Fold (Sec. 5.4), skip |w| > w_max, multiply by exp[i 2 pi w (n0 - 1)] (step 2),
-    and evaluate the W weights per axis."""
-    W = plan.W
+    and evaluate the weights per axis (W on u and v with lm, W_z on w with lmz,
+    by default lm)."""
+    W, lmz = plan.W, lm if lmz is None else lmz
     uvw_f, neg = _fold(uvw)
     V = np.asarray(vis, dtype=np.complex128).reshape(-1)
     V = np.where(neg, np.conj(V), V)
@@ -94,7 +116,7 @@ def grid_prepare(plan: Plan, lm: LeastMisfit, uvw, vis) -> GridInput:
     up, vp, wp = _normalised(plan, uvw_f)
     # n0 - 1 = -z_shift n_scale (eq. n_params; 0 without z offset)
     Vh = V * np.exp(2j * np.pi * uvw_f[:, 2] * (-plan.z_shift * plan.n_scale))
-    t_first, cz = _weights(lm, wp, W)
+    t_first, cz = _weights(lmz, wp, plan.W_z)
     r_first, cx = _weights(lm, up, W)
     s_first, cy = _weights(lm, vp, W)
     return GridInput(Vh, t_first, cz, r_first, cx, s_first, cy)
@@ -105,7 +127,7 @@ def grid_layer(plan: Plan, gi: GridInput, t: int) -> np.ndarray:
     then 2-D convolutional gridding with C_x, C_y.  Returns G_t [s, r]."""
     W, Np = plan.W, plan.Nprime
     c_idx = t - gi.t_first
-    k = np.nonzero((c_idx >= 0) & (c_idx < W))[0]
+    k = np.nonzero((c_idx >= 0) & (c_idx < plan.W_z))[0]
     if k.size == 0:
         return np.zeros((Np, Np), dtype=np.complex128)
     val = gi.Vh[k] * gi.cz[k, c_idx[k]]
@@ -121,7 +143,7 @@ def layer_image(plan: Plan, G: np.ndarray, t: int, z: np.ndarray) -> np.ndarray:
     """Steps 3b-3d: unnormalised 2-D IFFT, crop, phase exp(i 2 pi t z)."""
     Np = plan.Nprime
     crop = _crop(plan)
-    P = np.fft.ifft2(G) * (Np * Np)
+    P = scipy.fft.ifft2(G, workers=_WORKERS) * (Np * Np)
     return P[np.ix_(crop, crop)] * np.exp(2j * np.pi * t * z)
 
 
@@ -152,7 +174,7 @@ def degrid_layer(plan: Plan, g: np.ndarray, t: int, z: np.ndarray) -> np.ndarray
     crop = _crop(plan)
     pad = np.zeros((Np, Np), dtype=np.complex128)
     pad[np.ix_(crop, crop)] = g * np.exp(-2j * np.pi * t * z)
-    return np.fft.fft2(pad)
+    return scipy.fft.fft2(pad, workers=_WORKERS)
 
 
 def degrid_correlate(plan: Plan, lm: LeastMisfit, uvw, stack: np.ndarray) -> np.ndarray:
