@@ -126,13 +126,36 @@ def traffic_for(kernel: str, prec: str):
     return t.get("per_launch_bytes", {}).get(f"{kernel}:{prec}")
 
 
+def issue_for(kernel: str, prec: str):
+    """VALU wave instructions per launch and their issue time from committed
+    rocprofv3 counter runs, if taken on the current sources (a wave64 VALU
+    instruction holds a SIMD for 4 cycles: 1024 SIMDs at 2.4 GHz)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    n = t.get("valu_per_launch", {}).get(f"{kernel}:{prec}")
+    if n is None:
+        return None
+    return {"valu_instr_per_launch": n, "valu_issue_ms": 4.0 * n / (1024 * 2.4e9) * 1e3}
+
+
 def cpu_baseline(w: dict, n_sample: int) -> dict:
     """The FP64 oracle, as written, timed on a bounded sample and scaled to the full call.
 
     Per-visibility steps are timed at two sample sizes (n and 2n) so that their
     fixed per-layer part (the oracle grids each layer through a full N'^2
-    bincount) and their per-visibility slope are separated; one layer's
-    transform and a slice of the correction map are timed and scaled.
+    bincount) and their per-visibility slope are separated; the degrid
+    correlation reads a stack whose every page holds data (each layer the
+    transform of a random image, not untouched zero pages).  Two layers' transforms
+    (IFFT, crop, w-screen; w-screen, pad, FFT) and a slice of the correction
+    map are timed and scaled to all layers and pixels.  The 2-D transforms use
+    every host core (scipy.fft workers); every other step runs on one.
     """
     import numpy as np
 
@@ -154,7 +177,15 @@ def cpu_baseline(w: dict, n_sample: int) -> dict:
             G = wstack.grid_layer(plan, gi, t)
         return time.perf_counter() - t0, G
 
-    stack = np.zeros((nl, plan.Nprime, plan.Nprime), dtype=np.complex128)   # untouched pages: zero page
+    # a stack with data in every layer: each layer the transform of a random image
+    t0 = time.perf_counter()
+    g = np.random.default_rng(3).standard_normal((plan.N, plan.N))
+    stack = np.empty((nl, plan.Nprime, plan.Nprime), dtype=np.complex128)
+    layer = wstack.degrid_layer(plan, g, plan.t_hi, z)
+    t_degrid_layer = time.perf_counter() - t0
+    for i in range(nl):
+        stack[i] = layer
+    measured += time.perf_counter() - t0
 
     def degrid_vis(n):
         t0 = time.perf_counter()
@@ -176,26 +207,82 @@ def cpu_baseline(w: dict, n_sample: int) -> dict:
     lm.h(z.ravel()[:n_pix])
     t_pix = time.perf_counter() - t0
     t_corr = t_pix * (plan.N * plan.N / n_pix)
-    g = np.ones((plan.N, plan.N))
-    t0 = time.perf_counter()
-    wstack.degrid_layer(plan, g, plan.t_hi, z)
-    t_degrid_layer = time.perf_counter() - t0
     del stack
-    measured += t_grid_layer + t_pix + t_degrid_layer
+    measured += t_grid_layer + t_pix
     t_grid = g_fixed + g_slope * M + nl * t_grid_layer + t_corr
     t_degrid = d_fixed + d_slope * M + nl * t_degrid_layer + t_corr
+    cpus = os.cpu_count() or 1
     return {
         "value": M / (t_grid + t_degrid),
         "unit": "visibilities/s",
-        "cores": 1,
+        "cores": cpus,
         "kind": "oracle",
         "sample": (f"oracle per-visibility steps (fold, phase, weights, w-spreading and uv-gridding into all "
-                   f"{nl} layers; 3-D correlation) on the first {n1} and {n2} visibilities (fixed + per-"
-                   f"visibility fit), one layer's {plan.Nprime}^2 IFFT/crop/w-screen and one layer's pad/FFT, "
-                   f"h_z on {n_pix} pixels; scaled to {M} visibilities, {nl} layers, {plan.N}^2 pixels; "
-                   f"{measured:.1f} s measured, numpy single-threaded"),
+                   f"{nl} layers; 3-D correlation from a filled {nl}-layer stack) on the first {n1} and {n2} "
+                   f"visibilities (fixed + per-visibility fit), one layer's {plan.Nprime}^2 IFFT/crop/w-screen "
+                   f"and one layer's pad/FFT, h_z on {n_pix} pixels; scaled to {M} visibilities, {nl} layers, "
+                   f"{plan.N}^2 pixels; {measured:.1f} s measured; 2-D transforms on {cpus} threads (scipy.fft "
+                   f"workers), all other steps numpy on one"),
+        "host_cpus": cpus,
         "est_s_per_call": {"grid": t_grid, "degrid": t_degrid},
     }
+
+
+def bandwidth_probe(dev, gb: float = 4.0, repeats: int = 5) -> dict:
+    """Achievable HBM read + write rate: the library's streaming copy kernel
+    over gb GB (src -> dst), timed with events on the launch stream."""
+    import torch
+
+    from paper_2101_11172_amd import wsgrid
+
+    n = int(gb * 1e9) // 16 * 16
+    src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream(dev)
+    wsgrid.wsg_bandwidth_probe(src.data_ptr(), dst.data_ptr(), n, stream.cuda_stream)   # warm-up
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(repeats):
+        wsgrid.wsg_bandwidth_probe(src.data_ptr(), dst.data_ptr(), n, stream.cuda_stream)
+    b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / repeats
+    ok = bool(torch.equal(src[-1024:], dst[-1024:]))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_read": n, "bytes_written": n, "ms": ms, "GBps": 2 * n / (ms * 1e-3) / 1e9, "copy_ok": ok}
+
+
+def dft_errors(plan, w: dict, uvw, dev, n_pix: int = 10000, n_vis: int = 10000) -> dict:
+    """Relative RMS error against the direct transform at sampled outputs, per
+    result and precision: the dirty map of the workload's visibilities at
+    n_pix random pixels, and the model visibilities of a 500-source sky at
+    n_vis random baselines (direct transform on the device, float64)."""
+    import numpy as np
+    import torch
+
+    from paper_2101_11172_amd import direct, inputs
+
+    N, L = w["N"], w["L"]
+    rng = np.random.default_rng(17)
+    rows, cols = rng.integers(0, N, n_pix), rng.integers(0, N, n_pix)
+    V = torch.from_numpy(w["vis"]).to(dev).to(torch.complex128)
+    exact_g = direct.dft_grid(uvw, V, N, L, rows, cols)
+    sky = torch.from_numpy(inputs.random_sky(N, 500, 9)).to(dev)
+    idx = torch.from_numpy(np.random.default_rng(8).choice(uvw.shape[0], n_vis, replace=False)).to(dev)
+    exact_d = direct.dft_degrid(uvw[idx].contiguous(), sky, N, L)
+    rows_t, cols_t = torch.from_numpy(rows).to(dev), torch.from_numpy(cols).to(dev)
+
+    def rel(a, b):
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+    out = {"grid_pixels": n_pix, "degrid_visibilities": n_vis}
+    for name, cdt, rdt in (("fp32", torch.complex64, torch.float32), ("fp64", torch.complex128, torch.float64)):
+        g = plan.grid(uvw, V.to(cdt))
+        out[f"grid_{name}"] = rel(g[rows_t, cols_t].double(), exact_g)
+        d = plan.degrid(uvw, sky.to(rdt))
+        out[f"degrid_{name}"] = rel(d[idx].to(torch.complex128), exact_d)
+    return out
 
 
 def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int, ws: dict, calls: int) -> dict:
@@ -388,6 +475,9 @@ def main() -> int:
     ap.add_argument("--fp64-steps", type=int, default=3, help="0 skips the FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=60000)
+    ap.add_argument("--probe-gb", type=float, default=4.0,
+                    help="bytes (GB) of the streaming copy that measures achievable HBM bandwidth (0: skip)")
+    ap.add_argument("--no-dft", action="store_true", help="skip the errors against the direct transform")
     ap.add_argument("--copy-gb", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GB (counter calibration)")
     ap.add_argument("--no-z-offset", action="store_true",
@@ -416,6 +506,10 @@ def main() -> int:
     from paper_2101_11172_amd import inputs, wsgrid
 
     dev = torch.device("cuda", 0)
+    probe = bandwidth_probe(dev) if args.probe_gb > 0 else None
+    if probe:
+        log(f"bandwidth probe: {probe['GBps']:.0f} GB/s read + write ({probe['ms']:.3f} ms for 2 x "
+            f"{probe['bytes_read'] / 1e9:.1f} GB)")
     if args.copy_gb > 0:
         n = int(args.copy_gb * 1e9) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -475,12 +569,23 @@ def main() -> int:
         acc = {"grid": relrms(out_img32.double(), out_img64),
                "degrid": relrms(out_vis32.to(torch.complex128), out_vis64)}
 
+    dft_err = None
+    if not args.no_dft:
+        log("errors against the direct transform at sampled outputs")
+        dft_err = dft_errors(plan, w, uvw, dev)
+        log(f"dft errors: {dft_err}")
+
     dom = max(tab32, key=lambda k: tab32[k]["ms"])
     d = tab32[dom]
+    achievable = probe["GBps"] if probe else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic_for(dom, "f32"),
+                "achievable": achievable, "frac_of_achievable": d["alg_GBps"] / achievable if achievable else None,
                 "alg_bytes_per_call": d["alg_bytes"], "ms_per_call": d["ms"],
                 "launches_per_call": d["launches_per_call"]}
+    issue = issue_for(dom, "f32")
+    if issue:
+        roofline["issue"] = {**issue, "valu_issue_frac": issue["valu_issue_ms"] / d["ms"]}
     total_alg = sum(stage_bytes(s, M, N, Np, nl, False, ws) for s in tab32)
     result = {
         "metric": (f"visibilities/s grid+degrid at W={W},x0={x0:g}, FP32 vs FP64"
@@ -506,6 +611,10 @@ def main() -> int:
                    "z_offset": not args.no_z_offset},
         "roofline": roofline,
         "whole_step_alg_GBps": total_alg / (ms32 * 1e-3) / 1e9,
+        "whole_step_frac_of_peak": total_alg / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "whole_step_frac_of_achievable": (total_alg / (ms32 * 1e-3) / 1e9 / achievable) if achievable else None,
+        "hbm_probe": probe,
+        "dft_error": dft_err,
         "fp64": fp64,
         "fp32_vs_fp64_rel_rms": acc,
         "stages": tab32,

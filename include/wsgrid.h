@@ -50,7 +50,8 @@ extern "C" {
 
 typedef struct wsg_plan wsg_plan;
 
-enum { WSG_F32 = 0, WSG_F64 = 1 };
+/* arithmetic precision of a call: float32 or float64 data and arithmetic */
+typedef enum wsg_prec { WSG_F32 = 0, WSG_F64 = 1 } wsg_prec;
 
 enum {
     WSG_OK = 0,
@@ -97,10 +98,11 @@ wsg_plan* grid_create_variant(int N, double L, int W, double x0, double wmax, in
 void grid_destroy(wsg_plan* plan);
 
 /*
- * Plan parameters (any output pointer may be NULL): FFT length N', first
- * layer t_lo, number of layers, n0, n_scale, and the design's error bound E.
+ * Plan parameters (any output pointer may be NULL): FFT length N', number of
+ * w-layers N_w' (t_lo .. t_hi), first layer t_lo, n0, n_scale (Sec. 5.3, eq.
+ * n_params) and the design's error bound E (eq. norm_bound).
  */
-int grid_plan_info(const wsg_plan* plan, int* Nprime, int* t_lo, int* n_layers,
+int grid_plan_info(const wsg_plan* plan, int* Nprime, int* n_layers, int* t_lo,
                    double* n0, double* n_scale, double* E);
 
 /*
@@ -111,7 +113,7 @@ int grid_plan_info(const wsg_plan* plan, int* Nprime, int* t_lo, int* n_layers,
  * (2 n_layers N N' complex), the binned visibility records (2 M records), the
  * degrid per-tile parts (8 M complex) and the bin tables.  0 on a bad argument.
  */
-size_t grid_workspace_bytes(const wsg_plan* plan, int prec, int64_t M);
+size_t grid_workspace_bytes(const wsg_plan* plan, wsg_prec prec, int64_t M);
 
 /*
  * Smallest workspace (bytes) a call accepts: the same buffers with the stack
@@ -122,7 +124,7 @@ size_t grid_workspace_bytes(const wsg_plan* plan, int prec, int64_t M);
  * result differs from one pass only by rounding order; degridding is the same
  * arithmetic).  0 on a bad argument.
  */
-size_t grid_workspace_bytes_min(const wsg_plan* plan, int prec, int64_t M);
+size_t grid_workspace_bytes_min(const wsg_plan* plan, wsg_prec prec, int64_t M);
 
 /*
  * Dirty map by Algorithm 5.
@@ -133,7 +135,7 @@ size_t grid_workspace_bytes_min(const wsg_plan* plan, int prec, int64_t M);
  *         the end of the call's work).
  * M = 0 gives an all-zero map (uvw and vis may then be NULL).
  */
-int grid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw,
+int grid_visibilities(const wsg_plan* plan, wsg_prec prec, int64_t M, const double* uvw,
                       const void* vis, void* dirty, void* ws, size_t ws_bytes, void* stream);
 
 /*
@@ -143,7 +145,7 @@ int grid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* u
  *   vis [M] complex (prec) device, overwritten;  ws as for grid_visibilities.
  * M = 0 does nothing but the layer transforms (uvw and vis may then be NULL).
  */
-int degrid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw,
+int degrid_visibilities(const wsg_plan* plan, wsg_prec prec, int64_t M, const double* uvw,
                         const void* image, void* vis, void* ws, size_t ws_bytes, void* stream);
 
 /*
@@ -169,9 +171,9 @@ int degrid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double*
  * WSG_EINVAL for nch outside [1, 64], a sum of M of 2^31 or more, or more than
  * 2^25 tiles over the channels.
  */
-int grid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int64_t* M, const double* uvw,
+int grid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* M, const double* uvw,
                             const void* vis, void* dirty, void* ws, size_t ws_bytes, void* stream);
-int degrid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int64_t* M, const double* uvw,
+int degrid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* M, const double* uvw,
                               const void* image, void* vis, void* ws, size_t ws_bytes, void* stream);
 
 /*
@@ -180,7 +182,7 @@ int degrid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int
  * smallest workspace the call accepts (one tile layer of 16 w-layers per
  * pass).  0 on a bad argument.
  */
-size_t grid_workspace_bytes_batch(const wsg_plan* plan, int prec, int nch, int64_t M, int min_passes);
+size_t grid_workspace_bytes_batch(const wsg_plan* plan, wsg_prec prec, int nch, int64_t M, int min_passes);
 
 /*
  * Virtual w-layers per layer pass that a call with nch channels, M
@@ -189,13 +191,24 @@ size_t grid_workspace_bytes_batch(const wsg_plan* plan, int prec, int nch, int64
  * WSG_EWORKSPACE when ws_bytes is below the minimum, WSG_EINVAL on a bad
  * argument.  Host only.
  */
-int grid_layers_per_pass(const wsg_plan* plan, int prec, int nch, int64_t M, size_t ws_bytes);
+int grid_layers_per_pass(const wsg_plan* plan, wsg_prec prec, int nch, int64_t M, size_t ws_bytes);
 
 /*
  * Number of visibilities skipped (|w| > wmax or non-finite) by the last call
- * that used workspace `ws`.  Waits for `stream`.  Returns < 0 on error.
+ * that used workspace `ws`.  Waits for `stream`.  Returns < 0 on error.  The
+ * count lives in the caller's workspace, so calls on one plan with distinct
+ * workspaces (several threads) each keep their own.
  */
 int64_t grid_skipped(const wsg_plan* plan, const void* ws, void* stream);
+
+/*
+ * The same count for the most recent grid/degrid call made with this plan (on
+ * any thread): the library remembers that call's workspace and stream, waits
+ * for the stream and reads the counter there.  Valid while that workspace is
+ * alive and not reused by another plan.  Returns < 0 when the plan has made no
+ * call yet or on a HIP error.
+ */
+int64_t grid_last_skipped(const wsg_plan* plan);
 
 /*
  * Measurement aid.  While enabled on the calling thread, every grid/degrid call
@@ -213,6 +226,16 @@ int64_t grid_skipped(const wsg_plan* plan, const void* ws, void* stream);
 #define WSG_NSTAGES 10
 void wsg_stage_timing(int enable);
 int wsg_stage_times(double* ms, int* launches, int n);
+
+/*
+ * Measurement aid: achievable HBM bandwidth.  Enqueues on `stream` one
+ * streaming copy kernel dst[i] = src[i] over `bytes` bytes (16-byte vectors,
+ * each byte read once and written once), so that bytes * 2 / its duration is
+ * the read + write rate the memory system sustains for a plain stream.  src
+ * and dst are device pointers, 16-byte aligned, not overlapping; bytes a
+ * multiple of 16.  WSG_EINVAL otherwise.
+ */
+int wsg_bandwidth_probe(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Message of the last error on this thread ("" if none). */
 const char* grid_last_error(void);

@@ -27,8 +27,13 @@ def tune_pass_layers(plan: "wg.Plan", uvw: torch.Tensor, counts, vis: torch.Tens
     """
     counts = [int(c) for c in counts]
     nch, M = len(counts), int(sum(counts))
+    # the same checks as Plan.grid_batch / Plan.degrid_batch, before any launch
+    plan.check_batch(uvw, counts, vis=vis)
+    plan.check_batch(uvw, counts, image=image)
     prec = wg.WSG_F32 if vis.dtype == torch.complex64 else wg.WSG_F64
     rdt = torch.float32 if prec == wg.WSG_F32 else torch.float64
+    if image.dtype != rdt:
+        raise ValueError("image precision must match the visibilities' (float32 with complex64)")
     least = wg.grid_workspace_bytes_batch(plan._p, prec, nch, M, True)
     top = min(wg.grid_workspace_bytes_batch(plan._p, prec, nch, M), int(max_workspace_bytes))
     if top < least:

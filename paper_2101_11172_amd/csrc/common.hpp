@@ -33,31 +33,6 @@ __device__ __forceinline__ void phase_turns(double f, double* s, double* c) {
     sincospi(2.0 * r, s, c);
 }
 
-// Sum over the 64 lanes of a wave, left in lane 63, with DPP moves (no LDS):
-// prefix sums inside each 16-lane row (row_shr 1, 2, 4, 8; lanes shifted in
-// from outside the row contribute 0), then row 0 -> 1 and 2 -> 3 (row_bcast 15)
-// and rows 0-1 -> 2-3 (row_bcast 31).  Masked rows keep `old` = 0.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_shift(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true));
-}
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_shift(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, true);
-    return __hiloint2double(hi, lo);
-}
-template <typename R>
-__device__ __forceinline__ R wave_sum_lane63(R x) {
-    x += dpp_shift<0x111, 0xf>(x);   // row_shr:1
-    x += dpp_shift<0x112, 0xf>(x);   // row_shr:2
-    x += dpp_shift<0x114, 0xf>(x);   // row_shr:4
-    x += dpp_shift<0x118, 0xf>(x);   // row_shr:8
-    x += dpp_shift<0x142, 0xa>(x);   // row_bcast:15 into rows 1, 3
-    x += dpp_shift<0x143, 0xc>(x);   // row_bcast:31 into rows 2, 3
-    return x;
-}
-
 // One binned visibility.  ruv packs the first support index along u (low 16
 // bits) and v (high 16 bits), both taken modulo N'; rt is the first support
 // layer counted from t_lo.  nu are the fractional offsets in [-1/2, 1/2).

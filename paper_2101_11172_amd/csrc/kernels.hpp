@@ -14,6 +14,29 @@ __global__ void k_fill(T* __restrict__ p, size_t n, T v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
+// Streaming copy for the bandwidth probe: each block walks kProbeUnroll
+// consecutive 16-byte vectors per thread per round (all loads issued before
+// the stores), rounds strided by the whole grid.
+constexpr int kProbeThreads = 256;
+constexpr int kProbeUnroll = 4;
+__global__ void __launch_bounds__(kProbeThreads) k_copy_probe(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                            size_t n) {
+    const size_t step = size_t(gridDim.x) * kProbeThreads * kProbeUnroll;
+    for (size_t base = size_t(blockIdx.x) * kProbeThreads * kProbeUnroll + threadIdx.x; base < n; base += step) {
+        uint4 v[kProbeUnroll];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) {
+            const size_t i = base + size_t(u) * kProbeThreads;
+            if (i < n) v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) {
+            const size_t i = base + size_t(u) * kProbeThreads;
+            if (i < n) dst[i] = v[u];
+        }
+    }
+}
+
 // ------------------------------------------------------ visibility binning --
 //
 // Hermitian fold (Sec. 5.4), normalised coordinates u' = (l_max/x0) u,

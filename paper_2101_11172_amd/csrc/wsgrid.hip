@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -90,6 +91,10 @@ struct wsg_plan {
     float* corr32 = nullptr;
     cpx<double>* tw64 = nullptr;
     cpx<float>* tw32 = nullptr;
+    // the most recent call's workspace and stream (grid_last_skipped)
+    mutable std::mutex last_mu;
+    mutable const void* last_ws = nullptr;
+    mutable void* last_stream = nullptr;
 
     int nbins() const { return nbr * nbs * nbt; }
 };
@@ -118,7 +123,7 @@ size_t al2m(size_t x) { return (x + (size_t(2) << 20) - 1) & ~((size_t(2) << 20)
 
 // Workspace for nch channels (M visibilities in all) taken in passes of
 // `tiles_per_pass` tile layers (kTileT virtual layers each).
-Layout layout_of(const wsg_plan* p, int prec, int64_t M, int tiles_per_pass, int nch = 1) {
+Layout layout_of(const wsg_plan* p, wsg_prec prec, int64_t M, int tiles_per_pass, int nch = 1) {
     Layout L{};
     const size_t cs = prec == WSG_F32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
     const size_t rs = prec == WSG_F32 ? sizeof(Rec<float>) : sizeof(Rec<double>);
@@ -319,7 +324,7 @@ __global__ void k_set_chan(ChanArgs ca, int nch, long long* __restrict__ coff, i
 // a: the input array, b: the output array; with M = 0 the visibility-sized
 // one of them may be null (nothing is read from or written to it).  Mc: the
 // nch channels' visibility counts (host); *M receives their sum.
-int check_call(const wsg_plan* plan, int prec, int nch, const int64_t* Mc, int64_t* M, const double* uvw,
+int check_call(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* Mc, int64_t* M, const double* uvw,
                const void* a, bool a_empty_ok, const void* b, bool b_empty_ok, void* ws, size_t ws_bytes,
                Layout* L) {
     if (!plan) return fail(WSG_EINVAL, "null plan");
@@ -510,6 +515,12 @@ int build_tables(wsg_plan* p) {
     return WSG_OK;
 }
 
+void remember_call(const wsg_plan* p, const void* ws, void* stream) {
+    std::lock_guard<std::mutex> g(p->last_mu);
+    p->last_ws = ws;
+    p->last_stream = stream;
+}
+
 void free_tables(wsg_plan* p) {
     void* ptrs[] = {p->poly64, p->poly32, p->corr64, p->corr32, p->tw64, p->tw32};
     for (void* q : ptrs)
@@ -645,7 +656,7 @@ void grid_destroy(wsg_plan* plan) {
     delete plan;
 }
 
-int grid_plan_info(const wsg_plan* plan, int* Nprime, int* t_lo, int* n_layers, double* n0, double* n_scale,
+int grid_plan_info(const wsg_plan* plan, int* Nprime, int* n_layers, int* t_lo, double* n0, double* n_scale,
                    double* E) {
     if (!plan) return fail(WSG_EINVAL, "null plan");
     if (Nprime) *Nprime = plan->pp.Nprime;
@@ -657,17 +668,17 @@ int grid_plan_info(const wsg_plan* plan, int* Nprime, int* t_lo, int* n_layers, 
     return WSG_OK;
 }
 
-size_t grid_workspace_bytes(const wsg_plan* plan, int prec, int64_t M) {
+size_t grid_workspace_bytes(const wsg_plan* plan, wsg_prec prec, int64_t M) {
     if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL) return 0;
     return layout_of(plan, prec, M, plan->nbt).total;
 }
 
-size_t grid_workspace_bytes_min(const wsg_plan* plan, int prec, int64_t M) {
+size_t grid_workspace_bytes_min(const wsg_plan* plan, wsg_prec prec, int64_t M) {
     if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL) return 0;
     return layout_of(plan, prec, M, 1).total;
 }
 
-int grid_layers_per_pass(const wsg_plan* plan, int prec, int nch, int64_t M, size_t ws_bytes) {
+int grid_layers_per_pass(const wsg_plan* plan, wsg_prec prec, int nch, int64_t M, size_t ws_bytes) {
     if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL || nch < 1 ||
         nch > kMaxChannels)
         return fail(WSG_EINVAL, "bad argument");
@@ -678,43 +689,73 @@ int grid_layers_per_pass(const wsg_plan* plan, int prec, int nch, int64_t M, siz
     return L.pass_layers;
 }
 
-size_t grid_workspace_bytes_batch(const wsg_plan* plan, int prec, int nch, int64_t M, int min_passes) {
+size_t grid_workspace_bytes_batch(const wsg_plan* plan, wsg_prec prec, int nch, int64_t M, int min_passes) {
     if (!plan || (prec != WSG_F32 && prec != WSG_F64) || M < 0 || M > 0x7fffffffLL || nch < 1 ||
         nch > kMaxChannels)
         return 0;
     return layout_of(plan, prec, M, min_passes ? 1 : nch * plan->nbt, nch).total;
 }
 
-int grid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int64_t* M, const double* uvw,
+int grid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* M, const double* uvw,
                             const void* vis, void* dirty, void* ws, size_t ws_bytes, void* stream) {
     Layout L;
     int64_t tot = 0;
     int rc = check_call(plan, prec, nch, M, &tot, uvw, vis, true, dirty, false, ws, ws_bytes, &L);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    remember_call(plan, ws, stream);
     return prec == WSG_F32 ? run<float>(plan, true, M, tot, uvw, vis, dirty, ws, L, s)
                            : run<double>(plan, true, M, tot, uvw, vis, dirty, ws, L, s);
 }
 
-int degrid_visibilities_batch(const wsg_plan* plan, int prec, int nch, const int64_t* M, const double* uvw,
+int degrid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* M, const double* uvw,
                               const void* image, void* vis, void* ws, size_t ws_bytes, void* stream) {
     Layout L;
     int64_t tot = 0;
     int rc = check_call(plan, prec, nch, M, &tot, uvw, image, false, vis, true, ws, ws_bytes, &L);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    remember_call(plan, ws, stream);
     return prec == WSG_F32 ? run<float>(plan, false, M, tot, uvw, image, vis, ws, L, s)
                            : run<double>(plan, false, M, tot, uvw, image, vis, ws, L, s);
 }
 
-int grid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* vis, void* dirty,
+int grid_visibilities(const wsg_plan* plan, wsg_prec prec, int64_t M, const double* uvw, const void* vis, void* dirty,
                       void* ws, size_t ws_bytes, void* stream) {
     return grid_visibilities_batch(plan, prec, 1, &M, uvw, vis, dirty, ws, ws_bytes, stream);
 }
 
-int degrid_visibilities(const wsg_plan* plan, int prec, int64_t M, const double* uvw, const void* image, void* vis,
+int degrid_visibilities(const wsg_plan* plan, wsg_prec prec, int64_t M, const double* uvw, const void* image, void* vis,
                         void* ws, size_t ws_bytes, void* stream) {
     return degrid_visibilities_batch(plan, prec, 1, &M, uvw, image, vis, ws, ws_bytes, stream);
+}
+
+int64_t grid_last_skipped(const wsg_plan* plan) {
+    if (!plan) return fail(WSG_EINVAL, "null plan");
+    const void* ws;
+    void* stream;
+    {
+        std::lock_guard<std::mutex> g(plan->last_mu);
+        ws = plan->last_ws;
+        stream = plan->last_stream;
+    }
+    if (!ws) return fail(WSG_EINVAL, "the plan has made no grid/degrid call");
+    return grid_skipped(plan, ws, stream);
+}
+
+int wsg_bandwidth_probe(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst || bytes % 16 || (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
+        return fail(WSG_EINVAL, "probe: 16-byte aligned pointers and a multiple of 16 bytes are required");
+    const char *a = static_cast<const char*>(src), *b = static_cast<const char*>(dst);
+    if (a < b + bytes && b < a + bytes) return fail(WSG_EINVAL, "probe: overlapping buffers");
+    const size_t n = bytes / 16;
+    if (n == 0) return WSG_OK;
+    const unsigned blocks = unsigned(std::min<size_t>((n + kProbeThreads * kProbeUnroll - 1) /
+                                                          (kProbeThreads * kProbeUnroll), 256 * 64));
+    hipLaunchKernelGGL(k_copy_probe, dim3(blocks), dim3(kProbeThreads), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+    WSG_HIP(hipGetLastError());
+    return WSG_OK;
 }
 
 int64_t grid_skipped(const wsg_plan* plan, const void* ws, void* stream) {

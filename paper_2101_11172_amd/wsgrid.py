@@ -50,6 +50,8 @@ _SIGNATURES = {
     "grid_layers_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                             ctypes.c_size_t]),
     "grid_skipped": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "grid_last_skipped": (ctypes.c_int64, [ctypes.c_void_p]),
+    "wsg_bandwidth_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "grid_last_error": (ctypes.c_char_p, []),
     "wsg_design_eval": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_double_p, _c_double_p,
                                        ctypes.c_int, _c_double_p, _c_double_p, _c_double_p]),
@@ -112,7 +114,7 @@ def grid_destroy(plan: int) -> None:
 def grid_plan_info(plan: int) -> dict:
     Np, tlo, nl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     n0, ns, E = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-    _err(lib().grid_plan_info(plan, Np, tlo, nl, n0, ns, E), "grid_plan_info")
+    _err(lib().grid_plan_info(plan, Np, nl, tlo, n0, ns, E), "grid_plan_info")
     return dict(Nprime=Np.value, t_lo=tlo.value, n_layers=nl.value, n0=n0.value, n_scale=ns.value, E=E.value)
 
 
@@ -177,6 +179,17 @@ def grid_skipped(plan: int, ws_ptr: int, stream: int) -> int:
     if n < 0:
         raise RuntimeError(f"grid_skipped failed: {lib().grid_last_error().decode()}")
     return int(n)
+
+
+def grid_last_skipped(plan: int) -> int:
+    n = lib().grid_last_skipped(plan)
+    if n < 0:
+        raise RuntimeError(f"grid_last_skipped failed: {lib().grid_last_error().decode()}")
+    return int(n)
+
+
+def wsg_bandwidth_probe(src_ptr: int, dst_ptr: int, nbytes: int, stream: int) -> None:
+    _err(lib().wsg_bandwidth_probe(src_ptr, dst_ptr, nbytes, stream), "wsg_bandwidth_probe")
 
 
 def grid_last_error() -> str:
@@ -280,6 +293,22 @@ class Plan:
             raise ValueError("uvw must be a contiguous float64 [M, 3] tensor on the plan's device")
         return uvw.shape[0]
 
+    def check_batch(self, uvw: torch.Tensor, counts, vis: torch.Tensor | None = None,
+                    image: torch.Tensor | None = None):
+        """Validate the inputs of a batched call (raises ValueError); returns (M, counts)."""
+        M = self._check_uvw(uvw)
+        counts = [int(c) for c in counts]
+        if not counts or min(counts) < 0 or sum(counts) != M:
+            raise ValueError("counts must be non-negative and add up to the number of visibilities")
+        if vis is not None and (vis.dtype not in (torch.complex64, torch.complex128) or vis.shape != (M,)
+                                or not vis.is_contiguous() or vis.device != self.device):
+            raise ValueError("vis must be a contiguous complex64/complex128 [M] tensor on the plan's device")
+        if image is not None and (image.dtype not in (torch.float32, torch.float64)
+                                  or image.shape != (len(counts), self.N, self.N)
+                                  or not image.is_contiguous() or image.device != self.device):
+            raise ValueError("image must be a contiguous float32/float64 [channels, N, N] tensor on the device")
+        return M, counts
+
     def grid(self, uvw: torch.Tensor, vis: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         M = self._check_uvw(uvw)
         if vis.dtype not in (torch.complex64, torch.complex128) or vis.shape != (M,) or not vis.is_contiguous() \
@@ -315,13 +344,7 @@ class Plan:
     def grid_batch(self, uvw: torch.Tensor, counts, vis: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """Dirty maps [len(counts), N, N] of channels whose visibilities are
         consecutive runs of counts[c] rows of uvw / entries of vis."""
-        M = self._check_uvw(uvw)
-        counts = [int(c) for c in counts]
-        if sum(counts) != M:
-            raise ValueError("counts must add up to the number of visibilities")
-        if vis.dtype not in (torch.complex64, torch.complex128) or vis.shape != (M,) or not vis.is_contiguous() \
-                or vis.device != self.device:
-            raise ValueError("vis must be a contiguous complex64/complex128 [M] tensor on the plan's device")
+        M, counts = self.check_batch(uvw, counts, vis=vis)
         prec = _PREC[vis.dtype]
         rdt = torch.float32 if prec == WSG_F32 else torch.float64
         shape = (len(counts), self.N, self.N)
@@ -338,14 +361,7 @@ class Plan:
                      out: torch.Tensor | None = None) -> torch.Tensor:
         """Model visibilities of channels c = 0.. from images [len(counts), N, N],
         concatenated in channel order."""
-        M = self._check_uvw(uvw)
-        counts = [int(c) for c in counts]
-        if sum(counts) != M:
-            raise ValueError("counts must add up to the number of visibilities")
-        shape = (len(counts), self.N, self.N)
-        if image.dtype not in (torch.float32, torch.float64) or image.shape != shape \
-                or not image.is_contiguous() or image.device != self.device:
-            raise ValueError("image must be a contiguous float32/float64 [channels, N, N] tensor on the device")
+        M, counts = self.check_batch(uvw, counts, image=image)
         prec = _PREC[image.dtype]
         cdt = torch.complex64 if prec == WSG_F32 else torch.complex128
         if out is None:

@@ -60,3 +60,12 @@ def test_design_rejects_bad_arguments():
 def test_create_without_device_fails_cleanly():
     assert not wg.lib().grid_create(256, 0.2, 7, 0.25, 300.0)
     assert "device" in wg.grid_last_error()
+
+
+def test_probe_and_last_skipped_reject_bad_arguments():
+    # argument checks happen before any device call
+    assert wg.lib().wsg_bandwidth_probe(16, 4096, 15, None) == wg.WSG_EINVAL       # not a multiple of 16
+    assert wg.lib().wsg_bandwidth_probe(8, 4096, 16, None) == wg.WSG_EINVAL        # misaligned
+    assert wg.lib().wsg_bandwidth_probe(4096, 4104, 64, None) == wg.WSG_EINVAL     # overlapping (and misaligned)
+    assert wg.lib().wsg_bandwidth_probe(4096, 4112, 64, None) == wg.WSG_EINVAL     # overlapping
+    assert wg.lib().grid_last_skipped(None) == wg.WSG_EINVAL
