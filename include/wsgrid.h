@@ -139,6 +139,28 @@ int grid_visibilities(const wsg_plan* plan, wsg_prec prec, int64_t M, const doub
                       const void* vis, void* dirty, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: as
+ * grid_visibilities, with the workspace taken from the library's own static
+ * device buffer of WSG_SCRATCH_BYTES, which every device the library runs on
+ * holds (its own copy) until the process ends.  The call allocates nothing
+ * and makes no blocking HIP call; the buffer's device address is looked up
+ * once per device when the first plan is created there.
+ *   uvw, vis, dirty: as for grid_visibilities (caller's device memory).
+ *   Returns WSG_EWORKSPACE when grid_workspace_bytes_min(plan, prec, M)
+ *   exceeds WSG_SCRATCH_BYTES (the layers are taken in passes, as with a
+ *   small workspace; only small plans and visibility counts fit, e.g. N' =
+ *   512 with 13 layers and 5,000 visibilities in float64).
+ * Every call on a device shares that device's buffer: the call clears what
+ * must start at zero itself, and calls that overlap on one device (several
+ * streams or threads) race and give wrong results.  grid_last_skipped(plan)
+ * reads the count of skipped visibilities from the buffer.
+ */
+#define WSG_SCRATCH_BYTES ((size_t)128 << 20)
+int grid_visibilities_noalloc(const wsg_plan* plan, wsg_prec prec, int64_t M, const double* uvw,
+                              const void* vis, void* dirty, void* stream);
+
+/*
  * Model visibilities by Algorithm 6 (exact adjoint of grid_visibilities under
  * Re <., .> on visibilities and <., .> on real images).
  *   uvw [M][3] float64 device;  image [N][N] real (prec) device;

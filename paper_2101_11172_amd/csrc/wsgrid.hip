@@ -51,6 +51,34 @@ int fail(int code, const std::string& msg) {
 
 constexpr int kMaxBins = 1 << 25;   // bins over all channels (the bin tables take ~50 bytes per bin)
 
+// Workspace of grid_visibilities_noalloc: one file-scope device array, which
+// each device that loads the library holds (its own copy) until the process
+// ends.  Host code never passes its name to a kernel (on the host the name is
+// a stand-in, not a device address): the address comes from
+// hipGetSymbolAddress, once per device, and only that pointer is used.
+constexpr size_t kScratchBytes = size_t(WSG_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device `dev` (which must be current),
+// looked up on the first request for that device.
+int scratch_on(int dev, void** ptr) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(WSG_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(WSG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return WSG_OK;
+}
+
 // per-thread stage timing (wsg_stage_timing / wsg_stage_times)
 struct StageEvent {
     int stage;
@@ -634,6 +662,11 @@ wsg_plan* grid_create_variant(int N, double L, int W, double x0, double wmax, in
             return nullptr;
         }
         p->kd = design_kernel(W, x0);
+        void* sp = nullptr;
+        if (scratch_on(dev, &sp) != WSG_OK) {     // set-up: the no-alloc call's workspace on this device
+            delete p;
+            return nullptr;
+        }
         if (build_tables(p) != WSG_OK) {
             free_tables(p);
             delete p;
@@ -723,6 +756,22 @@ int degrid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, cons
 int grid_visibilities(const wsg_plan* plan, wsg_prec prec, int64_t M, const double* uvw, const void* vis, void* dirty,
                       void* ws, size_t ws_bytes, void* stream) {
     return grid_visibilities_batch(plan, prec, 1, &M, uvw, vis, dirty, ws, ws_bytes, stream);
+}
+
+int grid_visibilities_noalloc(const wsg_plan* plan, wsg_prec prec, int64_t M, const double* uvw, const void* vis,
+                              void* dirty, void* stream) {
+    if (!plan) return fail(WSG_EINVAL, "null plan");
+    if (prec != WSG_F32 && prec != WSG_F64) return fail(WSG_EINVAL, "prec must be WSG_F32 or WSG_F64");
+    if (M < 0 || M > 0x7fffffffLL) return fail(WSG_EINVAL, "M must be in [0, 2^31)");
+    const size_t need = grid_workspace_bytes_min(plan, prec, M);
+    if (need > kScratchBytes)
+        return fail(WSG_EWORKSPACE, "grid_visibilities_noalloc: the call needs " + std::to_string(need) +
+                                        " bytes of workspace, the library's scratch holds " +
+                                        std::to_string(kScratchBytes));
+    void* ws = nullptr;
+    const int rc = scratch_on(plan->device, &ws);
+    if (rc != WSG_OK) return rc;
+    return grid_visibilities_batch(plan, prec, 1, &M, uvw, vis, dirty, ws, kScratchBytes, stream);
 }
 
 int degrid_visibilities(const wsg_plan* plan, wsg_prec prec, int64_t M, const double* uvw, const void* image, void* vis,

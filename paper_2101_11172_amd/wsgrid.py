@@ -51,6 +51,8 @@ _SIGNATURES = {
                                             ctypes.c_size_t]),
     "grid_skipped": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "grid_last_skipped": (ctypes.c_int64, [ctypes.c_void_p]),
+    "grid_visibilities_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "wsg_bandwidth_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "grid_last_error": (ctypes.c_char_p, []),
     "wsg_design_eval": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_double_p, _c_double_p,
@@ -136,6 +138,12 @@ def grid_visibilities(plan: int, prec: int, M: int, uvw_ptr: int, vis_ptr: int, 
                       ws_ptr: int, ws_bytes: int, stream: int) -> None:
     _err(lib().grid_visibilities(plan, prec, M, uvw_ptr, vis_ptr, dirty_ptr, ws_ptr, ws_bytes, stream),
          "grid_visibilities")
+
+
+def grid_visibilities_noalloc(plan: int, prec: int, M: int, uvw_ptr: int, vis_ptr: int, dirty_ptr: int,
+                              stream: int) -> None:
+    _err(lib().grid_visibilities_noalloc(plan, prec, M, uvw_ptr, vis_ptr, dirty_ptr, stream),
+         "grid_visibilities_noalloc")
 
 
 def degrid_visibilities(plan: int, prec: int, M: int, uvw_ptr: int, image_ptr: int, vis_ptr: int,
