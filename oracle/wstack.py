@@ -67,21 +67,23 @@ def _weights(lm: LeastMisfit, xi: np.ndarray, W: int):
 _CORRECTIONS: dict = {}
 
 
-def correction(plan: Plan, lm: LeastMisfit) -> np.ndarray:
-    """h_x(x) h_y(y) h_z(z(x, y)) on the [j, i] pixel grid (Algorithm 5 step 5).
+def correction(plan: Plan, lm: LeastMisfit, lmz: LeastMisfit | None = None) -> np.ndarray:
+    """h_x(x) h_y(y) h_z(z(x, y)) on the [j, i] pixel grid (Algorithm 5 step 5);
+    h_x = h_y from lm, h_z from lmz (by default lm).
 
-    The map depends only on the plan and the design, so the last few are kept
+    The map depends only on the plan and the designs, so the last few are kept
     (read-only) for the next grid or degrid call."""
-    key = (plan, id(lm))
+    lmz = lm if lmz is None else lmz
+    key = (plan, id(lm), id(lmz))
     if key not in _CORRECTIONS:
         hx = lm.h(plan.pixel_x())
-        hz = lm.h(plan.z().ravel()).reshape(plan.N, plan.N)
+        hz = lmz.h(plan.z().ravel()).reshape(plan.N, plan.N)
         c = hx[None, :] * hx[:, None] * hz
         c.setflags(write=False)
         if len(_CORRECTIONS) >= 4:
             _CORRECTIONS.pop(next(iter(_CORRECTIONS)))
-        _CORRECTIONS[key] = (lm, c)
-    return _CORRECTIONS[key][1]
+        _CORRECTIONS[key] = (lm, lmz, c)
+    return _CORRECTIONS[key][2]
 
 
 def _crop(plan: Plan) -> np.ndarray:
@@ -147,9 +149,11 @@ def layer_image(plan: Plan, G: np.ndarray, t: int, z: np.ndarray) -> np.ndarray:
     return P[np.ix_(crop, crop)] * np.exp(2j * np.pi * t * z)
 
 
-def grid(plan: Plan, lm: LeastMisfit, uvw, vis, dump: dict | None = None) -> np.ndarray:
-    """Dirty map by Algorithm 5.  Returns the real [N, N] map."""
-    gi = grid_prepare(plan, lm, uvw, vis)
+def grid(plan: Plan, lm: LeastMisfit, uvw, vis, dump: dict | None = None,
+         lmz: LeastMisfit | None = None) -> np.ndarray:
+    """Dirty map by Algorithm 5.  Returns the real [N, N] map.  lmz: the w-axis
+    design (width plan.W_z, cropping plan.z0), by default lm."""
+    gi = grid_prepare(plan, lm, uvw, vis, lmz)
     z = plan.z()
     acc = np.zeros((plan.N, plan.N), dtype=np.complex128)
     stack = [] if dump is not None else None
@@ -158,7 +162,7 @@ def grid(plan: Plan, lm: LeastMisfit, uvw, vis, dump: dict | None = None) -> np.
         if stack is not None:
             stack.append(G)
         acc += layer_image(plan, G, t, z)              # step 4: accumulate
-    corr = correction(plan, lm)                         # step 5
+    corr = correction(plan, lm, lmz)                    # step 5
     if dump is not None:
         dump["stack"] = np.array(stack)
         dump["acc"] = acc
@@ -177,21 +181,23 @@ def degrid_layer(plan: Plan, g: np.ndarray, t: int, z: np.ndarray) -> np.ndarray
     return scipy.fft.fft2(pad, workers=_WORKERS)
 
 
-def degrid_correlate(plan: Plan, lm: LeastMisfit, uvw, stack: np.ndarray) -> np.ndarray:
+def degrid_correlate(plan: Plan, lm: LeastMisfit, uvw, stack: np.ndarray,
+                     lmz: LeastMisfit | None = None) -> np.ndarray:
     """Steps 4-5: 3-D correlation with C_x C_y C_z, phase exp[-i 2 pi w (n0 - 1)],
     conjugate for folded visibilities (Sec. 5.4)."""
-    W, Np = plan.W, plan.Nprime
+    W, Wz, Np = plan.W, plan.W_z, plan.Nprime
+    lmz = lm if lmz is None else lmz
     uvw_f, neg = _fold(uvw)
     out = np.zeros(uvw_f.shape[0], dtype=np.complex128)
     keep = np.nonzero(uvw_f[:, 2] <= plan.wmax)[0]
-    aW = np.arange(W)
+    aW, aWz = np.arange(W), np.arange(Wz)
     for lo in range(0, keep.size, 4096):
         k = keep[lo:lo + 4096]
         up, vp, wp = _normalised(plan, uvw_f[k])
-        t_first, cz = _weights(lm, wp, W)
+        t_first, cz = _weights(lmz, wp, Wz)
         r_first, cx = _weights(lm, up, W)
         s_first, cy = _weights(lm, vp, W)
-        tt = (t_first[:, None] + aW[None, :]) - plan.t_lo                 # [nk, W]
+        tt = (t_first[:, None] + aWz[None, :]) - plan.t_lo                # [nk, W_z]
         ss = (s_first[:, None] + aW[None, :]) % Np
         rr = (r_first[:, None] + aW[None, :]) % Np
         vals = stack[tt[:, :, None, None], ss[:, None, :, None], rr[:, None, None, :]]
@@ -202,15 +208,16 @@ def degrid_correlate(plan: Plan, lm: LeastMisfit, uvw, stack: np.ndarray) -> np.
     return out
 
 
-def degrid(plan: Plan, lm: LeastMisfit, uvw, image, dump: dict | None = None) -> np.ndarray:
-    """Model visibilities by Algorithm 6.  Returns complex [M]."""
+def degrid(plan: Plan, lm: LeastMisfit, uvw, image, dump: dict | None = None,
+           lmz: LeastMisfit | None = None) -> np.ndarray:
+    """Model visibilities by Algorithm 6.  Returns complex [M].  lmz as for grid."""
     N, Np = plan.N, plan.Nprime
     f = np.asarray(image, dtype=np.float64).reshape(N, N)
-    g = f * correction(plan, lm)                         # step 2
+    g = f * correction(plan, lm, lmz)                    # step 2
     z = plan.z()
     stack = np.zeros((plan.n_layers, Np, Np), dtype=np.complex128)
     for t in range(plan.t_lo, plan.t_hi + 1):            # step 3
         stack[t - plan.t_lo] = degrid_layer(plan, g, t, z)
     if dump is not None:
         dump["stack"] = stack
-    return degrid_correlate(plan, lm, uvw, stack)        # steps 4-5
+    return degrid_correlate(plan, lm, uvw, stack, lmz)   # steps 4-5

@@ -119,7 +119,7 @@ def test_planted_mistakes_are_caught(monkeypatch):
     # (1) h_z dropped from the correction
     orig_corr = wstack.correction
 
-    def no_hz(plan, lmf):
+    def no_hz(plan, lmf, lmz=None):
         hx = lmf.h(plan.pixel_x())
         return hx[None, :] * hx[:, None]
     monkeypatch.setattr(wstack, "correction", no_hz)
