@@ -459,7 +459,7 @@ __global__ void k_tile_list(const uint8_t* __restrict__ occ, const uint32_t* __r
 // Kernel polynomial degree in nu per precision (the host fits both).
 template <typename R>
 struct KernelDegree {
-    static constexpr int value = sizeof(R) == 8 ? 16 : 10;
+    static constexpr int value = sizeof(R) == 8 ? 16 : 8;
 };
 
 // The records that reach one tile: ranges [lo[g], lo[g] + off[g+1] - off[g])
@@ -514,11 +514,11 @@ __device__ __forceinline__ void tile_segments(const uint32_t* __restrict__ start
     }
 }
 
-// record array index of virtual position v (and, optionally, its range)
-__device__ __forceinline__ uint32_t seg_index(const TileSegs& sg, int n, uint32_t v, int* range = nullptr) {
-    int g = 0;
-    for (int k = 1; k < n; ++k) g += sg.off[k] <= v ? 1 : 0;
-    if (range) *range = g;
+// Record array index of virtual position v; g is the caller's current range,
+// moved forward to the one holding v (a lane's positions only grow, so the
+// search is incremental).
+__device__ __forceinline__ uint32_t seg_advance(const TileSegs& sg, int n, uint32_t v, int& g) {
+    while (g + 1 < n && sg.off[g + 1] <= v) ++g;
     return sg.lo[g] + (v - sg.off[g]);
 }
 
@@ -607,24 +607,27 @@ struct ScatterCfg {
     // (FP64: two), else 32 (two lanes each)
     static constexpr int kWaveBatch = W <= 7 ? 16 : 32;
     static constexpr int kLanesPerRecord = 64 / kWaveBatch;
-    static constexpr int kSlots = 4 * kWaveBatch;
+    // waves per block, each on its own part of the tile's record list (eight
+    // waves at three blocks per CU measured 13 % slower than four at four)
+    static constexpr int kWaves = 4;
+    static constexpr int kThreads = 64 * kWaves;
+    static constexpr int kSlots = kWaves * kWaveBatch;
     static constexpr int kPairs = W * W;
     static constexpr int kPI = (kPairs + 63) / 64;                // (x, y) residue pairs per lane
     static constexpr int kCells = kTileT * kTileR * kTileS;
-    static constexpr int kWords = ((W + 1) * sizeof(R) + 15) / 16 * 16 / sizeof(R);   // 16-byte rows
+    static constexpr int kWords = (W * sizeof(R) + 15) / 16 * 16 / sizeof(R);   // 16-byte rows
 };
 
 template <typename R, int W>
 struct __align__(16) ScatterStage {
-    // layer weights rotated (position (a + dt) mod W holds C(s_a - nu_w)),
-    // then the packed support start (dr + 128) | (ds + 128) << 8 | (dt + 128) << 16
+    // layer weights rotated (position (a + dt) mod W holds C(s_a - nu_w))
     R words[ScatterCfg<R, W>::kSlots][ScatterCfg<R, W>::kWords];
     // value times u weights (real, imaginary), rotated by dr; v weights rotated by ds
     R wuv[ScatterCfg<R, W>::kSlots][3 * W];
 };
 
 template <typename R, int W>
-__global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ rec,
+__global__ void __launch_bounds__((ScatterCfg<R, W>::kThreads)) k_grid_tiles(const Rec<R>* __restrict__ rec,
                                                     const uint32_t* __restrict__ start,
                                                     const uint32_t* __restrict__ cls,
                                                     const uint32_t* __restrict__ tlist,
@@ -645,14 +648,15 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
 
+    constexpr int NT = Cfg::kThreads, NW = Cfg::kWaves;
     if (tid < 64) tile_segments(start, cls, P, bt, bs, br, sg);
-    for (int i = tid; i < Cfg::kCells; i += 256) tre[i] = tim[i] = R(0);
+    for (int i = tid; i < Cfg::kCells; i += NT) tre[i] = tim[i] = R(0);
     __syncthreads();
     const int nseg = sg.n;
     const uint32_t total = sg.off[nseg];
-    // this wave's quarter of the list
-    const uint32_t quarter = (total + 3) / 4;
-    const uint32_t q0 = min(total, quarter * uint32_t(wv)), q1 = min(total, q0 + quarter);
+    // this wave's part of the list
+    const uint32_t part = (total + NW - 1) / NW;
+    const uint32_t q0 = min(total, part * uint32_t(wv)), q1 = min(total, q0 + part);
 
     if (q1 > q0) {
         // the lane's residue pairs, owned cells and register sums
@@ -731,15 +735,21 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
         static_assert(WB * LPR == 64, "the wave stages WB records with LPR lanes each");
         constexpr int A0 = (W + LPR - 1) / LPR;
         const int rl = lane & (WB - 1), half = lane / WB;
-        Rec<R> nxt;
-        if (q0 + uint32_t(rl) < q1) nxt = rec[seg_index(sg, nseg, q0 + uint32_t(rl))];
+        // the lane's next record: virtual position vn in range g (ranges only
+        // move forward as vn grows by WB per round)
+        uint32_t vn = q0 + uint32_t(rl);
+        int g = 0;
+        Rec<R> nxt{};
+        if (vn < q1) nxt = rec[seg_advance(sg, nseg, vn, g)];
         for (uint32_t base = q0; base < q1; base += WB) {
-            const int n = int(min(uint32_t(WB), q1 - base));
+            const int n = __builtin_amdgcn_readfirstlane(int(min(uint32_t(WB), q1 - base)));
+            // support start of this lane's record, relative to the tile, packed
+            const int dr = wrap_offset(int(nxt.ruv & 0xffffu), r0, P.Np);
+            const int ds = wrap_offset(int(nxt.ruv >> 16), s0, P.Np);
+            const int dt = int(nxt.rt) - t0;
+            const int d = (dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16);
             if (rl < n) {
                 // stage: rotated weights, value folded into the u weights
-                const int dr = wrap_offset(int(nxt.ruv & 0xffffu), r0, P.Np);
-                const int ds = wrap_offset(int(nxt.ruv >> 16), s0, P.Np);
-                const int dt = int(nxt.rt) - t0;
                 const int pr = mod_w<W>(dr), ps = mod_w<W>(ds), pt = mod_w<W>(dt);
                 const int slot = slot0 + rl;
 #pragma unroll
@@ -765,34 +775,52 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
                         st.words[slot][kt] = ht;
                     }
                 }
-                if (half == 0)
-                    st.words[slot][W] = bits_to_word((dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16), R(0));
             }
+            // slots whose support start differs from the previous slot's (slot 0:
+            // from the wave's current one): a scalar bit mask, so that the
+            // per-record check below costs no vector instruction
+            const int d_before = __shfl_up(d, 1, 64);
+            const bool moved = half == 0 && rl < n && (rl == 0 ? d != prev : d != d_before);
+            const uint64_t move_mask = __ballot(moved);
             wave_sync();
-            const uint32_t vn = base + WB + uint32_t(rl);
-            if (vn < q1) nxt = rec[seg_index(sg, nseg, vn)];
+            vn += WB;
+            if (vn < q1) nxt = rec[seg_advance(sg, nseg, vn, g)];
 
-            for (int j = 0; j < n; ++j) {
-                const int slot = slot0 + j;
-                R wt[W];
+            // groups of four slots with fixed offsets (one address update per
+            // group); each slot's stage values are read while the previous
+            // slot's products are formed
+            struct Slot {
+                R wt[W], fx[PI], fy[PI], fv[PI];
+            };
+            auto read_slot = [&](int slot, Slot& q) {
 #pragma unroll
-                for (int a = 0; a < W; ++a) wt[a] = st.words[slot][a];       // broadcast
-                const int d = __builtin_amdgcn_readfirstlane(word_bits(st.words[slot][W]));
-                R fx[PI], fy[PI], fv[PI];
+                for (int a = 0; a < W; ++a) q.wt[a] = st.words[slot][a];       // broadcast
 #pragma unroll
                 for (int i = 0; i < PI; ++i) {
-                    fx[i] = st.wuv[slot][px[i]];
-                    fy[i] = st.wuv[slot][W + px[i]];
-                    fv[i] = st.wuv[slot][2 * W + py[i]];
+                    q.fx[i] = st.wuv[slot][px[i]];
+                    q.fy[i] = st.wuv[slot][W + px[i]];
+                    q.fv[i] = st.wuv[slot][2 * W + py[i]];
                 }
-                if (d != prev) move_to(d);
+            };
+            Slot q[2];            // slot j in q[j & 1]: two register sets, no copies
+            read_slot(slot0, q[0]);
+            for (int j0 = 0; j0 < n; j0 += 4) {
+                const uint32_t m4 = uint32_t(move_mask >> j0) & 15u;
 #pragma unroll
-                for (int i = 0; i < PI; ++i) {
-                    const R gx = fx[i] * fv[i], gy = fy[i] * fv[i];
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int j = j0 + jj;
+                    if (j >= n) break;
+                    if (j + 1 < n) read_slot(slot0 + j + 1, q[(jj + 1) & 1]);
+                    if (m4 & (1u << jj)) move_to(__builtin_amdgcn_readlane(d, j));
+                    const Slot& c = q[jj & 1];
 #pragma unroll
-                    for (int a = 0; a < W; ++a) {
-                        ax[i][a] += gx * wt[a];
-                        ay[i][a] += gy * wt[a];
+                    for (int i = 0; i < PI; ++i) {
+                        const R gx = c.fx[i] * c.fv[i], gy = c.fy[i] * c.fv[i];
+#pragma unroll
+                        for (int a = 0; a < W; ++a) {
+                            ax[i][a] += gx * c.wt[a];
+                            ay[i][a] += gy * c.wt[a];
+                        }
                     }
                 }
             }
@@ -805,7 +833,7 @@ __global__ void __launch_bounds__(256) k_grid_tiles(const Rec<R>* __restrict__ r
     }
     __syncthreads();
     // write the tile: rows of kTileS cells
-    for (int i = tid; i < nt_valid * kTileR * kTileS; i += 256) {
+    for (int i = tid; i < nt_valid * kTileR * kTileS; i += NT) {
         const int ss = i % kTileS, rr = (i / kTileS) % kTileR, tt = i / (kTileR * kTileS);
         stack[((size_t)(t0 - P.pl0 + tt) * P.Np + (r0 + rr)) * P.Np + (s0 + ss)] = cpx<R>{tre[i], tim[i]};
     }
@@ -868,7 +896,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     uint32_t nxt_p = 0, nxt_m = 0;
     int g_ = 0;
     if (q0 + uint32_t(lane) < q1) {
-        nxt_p = seg_index(sg, nseg, q0 + uint32_t(lane), &g_);
+        nxt_p = seg_advance(sg, nseg, q0 + uint32_t(lane), g_);
         nxt_m = sg.nbr[g_];
         nxt = rec[nxt_p];
     }
@@ -890,7 +918,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const uint32_t p = nxt_p, m = nxt_m;
         const uint32_t vn = base + WB + uint32_t(lane);
         if (vn < q1) {
-            nxt_p = seg_index(sg, nseg, vn, &g_);
+            nxt_p = seg_advance(sg, nseg, vn, g_);
             nxt_m = sg.nbr[g_];
             nxt = rec[nxt_p];
         }

@@ -229,7 +229,8 @@ void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* s
                     const uint32_t* tlist, const uint32_t* tpos, const DevParams& P, const R* coef, cpx<R>* stack,
                     cpx<R>* part, size_t part_stride, hipStream_t s) {
     if (grid)
-        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, tlist, tpos, P,
+        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(ScatterCfg<R, W>::kThreads), 0, s, rec, start,
+                           cls, tlist, tpos, P,
                            coef, stack);
     else
         hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, tlist, tpos, P,
