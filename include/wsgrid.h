@@ -61,12 +61,19 @@ enum {
     WSG_EHIP = -4         /* HIP runtime error (no device, launch failure, ...)   */
 };
 
+/* w-layer method of a plan (see grid_create_axes) */
+typedef enum wsg_method {
+    WSG_IMPROVED = 0,             /* improved W-stacking, z offset (eq. n_params)         */
+    WSG_IMPROVED_NO_OFFSET = 1,   /* improved W-stacking without z offset (Sec. 5.3)     */
+    WSG_ORIGINAL = 2              /* original W-stacking, Algorithms 3 and 4 (Sec. 4)    */
+} wsg_method;
+
 /*
  * Create a plan for an N x N image spanning L in direction cosine (l, m in
  * [-L/2, L/2)), gridding width W in u, v and w, cropping parameter x0 (= y0 =
  * z0, Sec. 6.2) and largest |w| = wmax wavelengths.
- *   - FFT length N' = N / (2 x0) (Algorithm 1); must be a power of two in
- *     [64, 8192].
+ *   - FFT length N' = N / (2 x0) (Algorithm 1); must be 2^a or 3 2^a (radix-3
+ *     transforms, e.g. x0 = 1/3, Sec. 6.3) in [64, 8192].
  *   - n_scale = (1 - n_min) / (2 z0), n0 = 1 - z0 n_scale (eq. n_params).
  *   - w-layers t = t_lo .. t_hi with t_lo = floor(W/2) - W + 1 and
  *     t_hi = floor(n_scale wmax + W/2) (Algorithm 5 step 1; every layer a
@@ -93,6 +100,40 @@ wsg_plan* grid_create(int N, double L, int W, double x0, double wmax);
  * ownership as grid_create.
  */
 wsg_plan* grid_create_variant(int N, double L, int W, double x0, double wmax, int z_offset);
+
+/*
+ * Plan with the gridding function chosen per axis and the w-layer method
+ * (Sec. 5.2: eqs. gridded-dirty-map and gridded_vis allow separate C_x, C_y,
+ * C_z; Sec. 6.1 trades W_z against z0; Sec. 4 and 6.2: the original method is
+ * the W_z = 1 top hat).
+ *   W, x0    width and cropping on u and v (the image axes);
+ *   Wz, z0   width and cropping on w (improved methods): n_scale = (1 -
+ *            n_min) / (2 z0) and n0 = 1 - z0 n_scale (WSG_IMPROVED) or n_scale
+ *            = (1 - n_min) / z0 and n0 = 1 (WSG_IMPROVED_NO_OFFSET); layers
+ *            t = floor(Wz/2) - Wz + 1 .. floor(n_scale wmax + Wz/2); the
+ *            correction is h_x h_y h_z with h_z of the (Wz, z0) design;
+ *   method   WSG_ORIGINAL: Algorithms 3 and 4 -- Wz must be 1 (z0 ignored),
+ *            n_bins bins over [0, wmax] after the Hermitian fold (0: the
+ *            smallest count of eq. N_w, ceil(2 pi (1 - n_min) wmax)); a
+ *            visibility goes to bin t = floor(w / dw), dw = wmax / n_bins (the
+ *            last bin closed), with weight 1 and the bin phase exp(+-i 2 pi
+ *            w[t] (n - 1)) at the midpoint w[t] = (t + 1/2) dw; the correction
+ *            is h_x h_y only.
+ * Compiled width pairs: Wz = W with z0 = x0 (W = 1 .. 16); otherwise W = 7 with
+ * Wz = 1 .. 7, or Wz = 1 with W = 3 .. 8.  Other pairs give WSG_EINVAL.
+ * grid_create(N, L, W, x0, wmax) is grid_create_axes(N, L, W, x0, W, x0, wmax,
+ * WSG_IMPROVED, 0).  NULL on error; ownership as for grid_create.
+ */
+wsg_plan* grid_create_axes(int N, double L, int W, double x0, int Wz, double z0, double wmax, wsg_method method,
+                           int n_bins);
+
+/*
+ * Axis parameters of a plan (any output pointer may be NULL): W, x0, W_z, z0
+ * (0 for the original method), the method, n_bins (original method, else 0)
+ * and the error bound E of the w-axis design (NaN for the top hat).
+ */
+int grid_plan_axes(const wsg_plan* plan, int* W, double* x0, int* Wz, double* z0, int* method, int* n_bins,
+                   double* E_z);
 
 /* Free a plan and its device tables (blocking).  NULL is ignored. */
 void grid_destroy(wsg_plan* plan);
@@ -278,6 +319,10 @@ int wsg_design_eval(int W, double x0, int n_nu, const double* nu, double* c_out,
  */
 int wsg_plan_params(int N, double L, int W, double x0, double wmax, int z_offset,
                     int* Nprime, int* t_lo, int* t_hi, double* n0, double* n_scale);
+
+/* Host-only planner of grid_create_axes (no GPU use, no design). */
+int wsg_plan_params_axes(int N, double L, int W, double x0, int Wz, double z0, double wmax, wsg_method method,
+                         int n_bins, int* Nprime, int* t_lo, int* t_hi, double* n0, double* n_scale);
 
 #ifdef __cplusplus
 }

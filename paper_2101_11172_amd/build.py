@@ -26,14 +26,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+SOURCES = ("wsgrid.hip", "tiles_f32.hip", "tiles_f64.hip", "fft_f32.hip", "fft_f64.hip", "design.cpp")
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source into libwsgrid.so (always recompiles)."""
-    srcs = [os.path.join(CSRC, "wsgrid.hip"), os.path.join(CSRC, "design.cpp")]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(HERE, "..", "include"), *srcs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    """Compile every source into libwsgrid.so (always recompiles; the units
+    compile in parallel, then link)."""
+    import tempfile
+
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    flags = [f for f in HIP_FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="wsgrid_build_") as tmpdir:
+        procs, objs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, src + ".o")
+            cmd = [hipcc(), *flags, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((src, subprocess.Popen(cmd)))
+            objs.append(obj)
+        failed = [src for src, p in procs if p.wait() != 0]
+        if failed:
+            raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
+        tmp = LIB + ".tmp"
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
 

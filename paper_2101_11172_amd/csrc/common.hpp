@@ -50,6 +50,10 @@ struct Rec {
 // Scalars every kernel needs, passed by value.
 struct DevParams {
     int N, Np, W, n_layers, t_lo;
+    int Wz;                 // width of the w-axis gridding function (W: the same on all axes)
+    int tclamp;             // original W-stacking: the last w bin is closed at wmax
+    double wshift;          // w' = n_scale w + wshift (original W-stacking: -1/2)
+    double tphase;          // layer t's w-screen uses t + tphase (original W-stacking: bin midpoints, 1/2)
     int nbr, nbs, nbt;      // bins (= tiles) along r (u), s (v), t (w) of one channel
     // Channels of a batched call: channel c's layers are the virtual layers
     // [c chl, c chl + n_layers) with chl = nbt kTileT (its tile layers follow

@@ -447,38 +447,85 @@ KernelDesign design_kernel(int W, double x0) {
     return D;
 }
 
-std::string make_plan_params(int N, double L, int W, double x0, double wmax, PlanParams* p, bool z_offset) {
+KernelDesign top_hat_design() {
+    KernelDesign D;
+    D.W = 1;
+    D.x0 = 0.5;
+    D.degree = kDegree;
+    D.poly.assign(size_t(kDegree) + 1, 0.0);
+    D.poly[0] = 1.0;
+    D.degree_lo = kDegreeLo;
+    D.poly_lo.assign(size_t(kDegreeLo) + 1, 0.0);
+    D.poly_lo[0] = 1.0;
+    D.E = std::nan("");
+    return D;
+}
+
+std::string make_plan_params_ext(int N, double L, int W, double x0, int Wz, double z0, double wmax, int method,
+                                 int n_bins, PlanParams* p) {
     if (N <= 0 || (N & 1)) return "N must be positive and even";
     if (!(x0 > 0.0 && x0 <= 0.5)) return "x0 must be in (0, 1/2]";
     if (W < 1 || W > 16) return "W must be in [1, 16]";
     if (!(L > 0.0 && L < std::sqrt(2.0))) return "L must be in (0, sqrt 2)";
     if (!(wmax >= 0.0) || !std::isfinite(wmax)) return "wmax must be finite and >= 0";
+    if (method != kImproved && method != kImprovedNoOffset && method != kOriginal) return "unknown w-layer method";
+    if (method == kOriginal) {
+        if (Wz != 1) return "the original W-stacking takes W_z = 1 (nearest w bin)";
+        if (!(wmax > 0.0)) return "the original W-stacking needs wmax > 0";
+        if (n_bins < 0 || n_bins > 1000000) return "n_bins must be in [0, 10^6]";
+    } else {
+        if (Wz < 1 || Wz > W) return "W_z must be in [1, W]";
+        if (!(z0 > 0.0 && z0 <= 0.5)) return "z0 must be in (0, 1/2]";
+    }
     double np = N / (2.0 * x0);
     long npr = std::lround(np);
     if (std::fabs(np - double(npr)) > 1e-9) return "N / (2 x0) must be an integer";
     p->N = N;
     p->L = L;
     p->W = W;
+    p->Wz = Wz;
     p->x0 = x0;
+    p->z0 = method == kOriginal ? 0.0 : z0;
     p->wmax = wmax;
+    p->method = method;
     p->Nprime = int(npr);
     p->l_max = 0.5 * L;
     p->n_min = std::sqrt(1.0 - 2.0 * p->l_max * p->l_max);
-    p->z_offset = z_offset;
-    if (z_offset) {
-        p->n_scale = (1.0 - p->n_min) / (2.0 * x0);     // eq. n_params with z0 = x0
-        p->n0 = 1.0 - x0 * p->n_scale;
-        p->z_shift = x0;
+    p->z_offset = method == kImproved;
+    p->w_shift = 0.0;
+    p->t_phase = 0.0;
+    if (method == kOriginal) {
+        // eq. N_w: the smallest integer >= 2 pi (n_max - n_min)(w_max - w_min), w_min = 0 after the fold
+        if (n_bins == 0) n_bins = std::max(1, int(std::ceil(2.0 * kPi * (1.0 - p->n_min) * wmax)));
+        p->n_bins = n_bins;
+        p->n_scale = double(n_bins) / wmax;
+        p->n0 = 1.0;
+        p->z_shift = 0.0;
+        p->w_shift = -0.5;
+        p->t_phase = 0.5;
+        p->t_lo = 0;
+        p->t_hi = n_bins - 1;
+        return std::string();
+    }
+    p->n_bins = 0;
+    if (method == kImproved) {
+        p->n_scale = (1.0 - p->n_min) / (2.0 * z0);     // eq. n_params
+        p->n0 = 1.0 - z0 * p->n_scale;
+        p->z_shift = z0;
     } else {
-        p->n_scale = (1.0 - p->n_min) / x0;             // eq. n_params_no_offset
+        p->n_scale = (1.0 - p->n_min) / z0;             // eq. n_params_no_offset
         p->n0 = 1.0;
         p->z_shift = 0.0;
     }
-    p->t_lo = W / 2 - W + 1;
-    double top = std::floor(p->n_scale * wmax + 0.5 * W);
+    p->t_lo = Wz / 2 - Wz + 1;
+    double top = std::floor(p->n_scale * wmax + 0.5 * Wz);
     if (top > 1e6) return "wmax too large: more than a million w-layers";
     p->t_hi = int(top);
     return std::string();
+}
+
+std::string make_plan_params(int N, double L, int W, double x0, double wmax, PlanParams* p, bool z_offset) {
+    return make_plan_params_ext(N, L, W, x0, W, x0, wmax, z_offset ? kImproved : kImprovedNoOffset, 0, p);
 }
 
 }  // namespace wsg

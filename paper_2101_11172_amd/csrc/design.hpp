@@ -33,18 +33,43 @@ struct KernelDesign {
 // Throws std::runtime_error on a bad argument.
 KernelDesign design_kernel(int W, double x0);
 
+// The top hat of the original W-stacking (Sec. 6.2): W = 1, C = 1 on the
+// unit interval (every polynomial coefficient but the constant is zero), no
+// correction (h = 1).
+KernelDesign top_hat_design();
+
+// w-layer methods: the improved W-stacking with (eq. n_params) or without
+// (eq. n_params_no_offset) the z offset, and the original W-stacking of
+// Algorithms 3 and 4 (nearest-midpoint w bins).
+enum PlanMethod { kImproved = 0, kImprovedNoOffset = 1, kOriginal = 2 };
+
 struct PlanParams {
     int N = 0, W = 0, Nprime = 0, t_lo = 0, t_hi = 0;
+    int Wz = 0;             // width of the w-axis gridding function
     double L = 0, x0 = 0, wmax = 0, l_max = 0, n_min = 0, n_scale = 0, n0 = 0;
+    double z0 = 0;          // w-axis cropping (improved methods)
+    int method = kImproved;
+    int n_bins = 0;         // original W-stacking: N_w
     bool z_offset = true;
     double z_shift = 0;     // (1 - n0) / n_scale: z = (n - 1) / n_scale + z_shift
+    double w_shift = 0;     // w' = n_scale w + w_shift (original: -1/2, so layer t holds t <= w / dw < t + 1)
+    double t_phase = 0;     // layer t's w-screen uses t + t_phase (original: 1/2, the bin midpoints)
     int n_layers() const { return t_hi - t_lo + 1; }
 };
 
 // Validates and fills the plan parameters; returns an empty string on success,
 // else the reason.
-// z_offset selects eq. n_params (z in [-z0, z0]) or, when false, the variant
-// without z offset, eq. n_params_no_offset (n0 = 1, z in [-z0, 0]; Sec. 5.3).
+//   improved methods: w axis of width Wz and cropping z0 (Sec. 5.2 allows a
+//     C_z of its own), n_scale and n0 from eq. n_params (z in [-z0, z0]) or eq.
+//     n_params_no_offset (n0 = 1, z in [-z0, 0]), layers t_lo = floor(Wz/2) -
+//     Wz + 1 .. floor(n_scale wmax + Wz/2);
+//   original W-stacking: Wz = 1 (top hat), n_bins bins over [0, wmax] (0: the
+//     smallest count of eq. N_w), n_scale = n_bins / wmax, n0 = 1, layers
+//     0 .. n_bins - 1 at the midpoints (t + 1/2) / n_scale.
+std::string make_plan_params_ext(int N, double L, int W, double x0, int Wz, double z0, double wmax, int method,
+                                 int n_bins, PlanParams* p);
+// Improved method with the same (W, x0) on all axes; z_offset selects eq.
+// n_params or eq. n_params_no_offset.
 std::string make_plan_params(int N, double L, int W, double x0, double wmax, PlanParams* p, bool z_offset = true);
 
 }  // namespace wsg

@@ -1,9 +1,12 @@
-// Batched 1-D FFT of length N = 2^LOGN for one line held by T = N/16 threads.
+// Batched 1-D FFT of length N = 2^a or 3 2^a for one line held by T = N/16
+// threads.
 //
 // Stockham autosort: radix-16 passes in registers with the exchanges between
-// passes through an LDS line buffer, and a final radix-2/4/8 pass when LOGN is
-// not a multiple of 4.  On entry thread j holds x[j + T k] (k = 0..15); on exit
-// it holds X[j + T k], where X[f] = sum_n x[n] exp(DIR i 2 pi n f / N), unnormalised.
+// passes through an LDS line buffer, a radix-2/4/8 pass when log2 of the
+// power-of-two part is not a multiple of 4, and for N = 3 2^a a last radix-3
+// pass done in place in the LDS buffer (N/3 butterflies shared out over the T
+// threads).  On entry thread j holds x[j + T k] (k = 0..15); on exit it holds
+// X[j + T k], where X[f] = sum_n x[n] exp(DIR i 2 pi n f / N), unnormalised.
 // Twiddles come from a float64-derived table tw[k] = exp(+i 2 pi k / N).
 #pragma once
 #include "common.hpp"
@@ -115,16 +118,26 @@ __device__ __forceinline__ cpx<R> twiddle(const cpx<R>* __restrict__ tw, int k) 
     return w;
 }
 
+// log2 of a power of two
+template <int N>
+constexpr int log2_of() {
+    int l = 0;
+    while ((1 << l) < N) ++l;
+    return l;
+}
+
 // In-place FFT of one line; `buf` is this line's LDS buffer of LinePad<N>::size
 // elements.  Every thread of the block must call this the same number of times
 // (it contains __syncthreads).
-template <typename R, int LOGN, int DIR>
-__device__ __forceinline__ void fft_line(cpx<R> (&v)[16], cpx<R>* buf, const cpx<R>* __restrict__ tw,
-                                         int j) {
-    constexpr int N = 1 << LOGN;
+template <typename R, int N, int DIR>
+__device__ __forceinline__ void fft_line(cpx<R> (&v)[16], cpx<R>* buf, const cpx<R>* __restrict__ tw, int j) {
+    constexpr bool R3 = N % 3 == 0;
+    constexpr int NP2 = R3 ? N / 3 : N;               // power-of-two part
+    constexpr int LOG2 = log2_of<NP2>();
+    static_assert((1 << LOG2) == NP2 && N % 16 == 0, "N = 2^a or 3 2^a, a multiple of 16");
     constexpr int T = N / 16;
-    constexpr int P16 = LOGN / 4;
-    constexpr int REM = LOGN % 4;
+    constexpr int P16 = LOG2 / 4;
+    constexpr int REM = LOG2 % 4;
     int Ns = 1;
 #pragma unroll
     for (int p = 0; p < P16; ++p) {
@@ -134,10 +147,10 @@ __device__ __forceinline__ void fft_line(cpx<R> (&v)[16], cpx<R>* buf, const cpx
             const int k = j & (Ns - 1);
             const int stride = N / (Ns * 16);
 #pragma unroll
-            for (int m = 1; m < 16; ++m) v[m] = cmul(v[m], twiddle<R, DIR>(tw, (k * m * stride) & (N - 1)));
+            for (int m = 1; m < 16; ++m) v[m] = cmul(v[m], twiddle<R, DIR>(tw, k * m * stride));
         }
         dft16<R, DIR>(v);
-        if (REM == 0 && p == P16 - 1) return;   // natural order: v[m] = X[j + m T]
+        if (!R3 && REM == 0 && p == P16 - 1) return;   // natural order: v[m] = X[j + m T]
         __syncthreads();
         const int base = (j / Ns) * Ns * 16 + (j & (Ns - 1));
 #pragma unroll
@@ -146,9 +159,10 @@ __device__ __forceinline__ void fft_line(cpx<R> (&v)[16], cpx<R>* buf, const cpx
         Ns *= 16;
     }
     if constexpr (REM > 0) {
-        constexpr int RR = 1 << REM;      // last radix
+        constexpr int RR = 1 << REM;      // radix of this pass
         constexpr int B = 16 / RR;        // butterflies per thread
-        constexpr int NR = N / RR;        // = Ns
+        constexpr int NR = N / RR;        // butterfly stride (= Ns when this is the last pass)
+        constexpr int TWS = R3 ? 3 : 1;   // N / (Ns RR)
         cpx<R> u[16];
 #pragma unroll
         for (int b = 0; b < B; ++b)
@@ -156,18 +170,52 @@ __device__ __forceinline__ void fft_line(cpx<R> (&v)[16], cpx<R>* buf, const cpx
             for (int m = 0; m < RR; ++m) u[b * RR + m] = buf[lpad(j + b * T + m * NR)];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int k = (j + b * T) & (NR - 1);
+            const int k = (j + b * T) & (Ns - 1);
 #pragma unroll
-            for (int m = 1; m < RR; ++m) u[b * RR + m] = cmul(u[b * RR + m], twiddle<R, DIR>(tw, k * m));
+            for (int m = 1; m < RR; ++m) u[b * RR + m] = cmul(u[b * RR + m], twiddle<R, DIR>(tw, k * m * TWS));
             if constexpr (RR == 2) dft2<R, DIR>(u[b * RR], u[b * RR + 1]);
             if constexpr (RR == 4) dft4<R, DIR>(u[b * RR], u[b * RR + 1], u[b * RR + 2], u[b * RR + 3]);
             if constexpr (RR == 8) dft8<R, DIR>(&u[b * RR]);
         }
-        // output X[j + b T + m' NR] = X[j + T (b + m' B)]
+        if constexpr (!R3) {
+            // output X[j + b T + m' NR] = X[j + T (b + m' B)]
 #pragma unroll
-        for (int b = 0; b < B; ++b)
+            for (int b = 0; b < B; ++b)
 #pragma unroll
-            for (int m = 0; m < RR; ++m) v[b + m * B] = u[b * RR + m];
+                for (int m = 0; m < RR; ++m) v[b + m * B] = u[b * RR + m];
+            return;
+        } else {
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int jb = j + b * T;
+                const int base = (jb / Ns) * Ns * RR + (jb & (Ns - 1));
+#pragma unroll
+                for (int m = 0; m < RR; ++m) buf[lpad(base + m * Ns)] = u[b * RR + m];
+            }
+            __syncthreads();
+            Ns *= RR;
+        }
+    }
+    if constexpr (R3) {
+        // last pass, radix 3 with Ns = N / 3: butterfly i reads and writes
+        // positions i, i + N/3, i + 2N/3 (natural order out), twiddles exp(DIR i 2 pi i m / N)
+        constexpr int N3 = N / 3;
+        const R hs = R(DIR) * R(0.86602540378443864676);      // DIR sin(2 pi / 3)
+        for (int i = j; i < N3; i += T) {
+            cpx<R> a = buf[lpad(i)], b = buf[lpad(i + N3)], c = buf[lpad(i + 2 * N3)];
+            b = cmul(b, twiddle<R, DIR>(tw, i));
+            c = cmul(c, twiddle<R, DIR>(tw, 2 * i));
+            const cpx<R> s1 = cadd(b, c), d1 = csub(b, c);
+            const cpx<R> m1 = {a.x - R(0.5) * s1.x, a.y - R(0.5) * s1.y};
+            const cpx<R> rot = {-hs * d1.y, hs * d1.x};         // DIR i sin(2 pi/3) (b - c)
+            buf[lpad(i)] = cadd(a, s1);
+            buf[lpad(i + N3)] = cadd(m1, rot);
+            buf[lpad(i + 2 * N3)] = csub(m1, rot);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = buf[lpad(j + m * T)];
     }
 }
 

@@ -1,4 +1,6 @@
 // wsgrid device kernels (gfx950).  See wsgrid.hip for the launch sequence.
+// The header is included by several compilation units: kernels that are not
+// templates are static (one copy per unit that launches them).
 #pragma once
 #include "common.hpp"
 #include "fft.hpp"
@@ -19,7 +21,7 @@ __global__ void k_fill(T* __restrict__ p, size_t n, T v) {
 // the stores), rounds strided by the whole grid.
 constexpr int kProbeThreads = 256;
 constexpr int kProbeUnroll = 4;
-__global__ void __launch_bounds__(kProbeThreads) k_copy_probe(const uint4* __restrict__ src, uint4* __restrict__ dst,
+static __global__ void __launch_bounds__(kProbeThreads) k_copy_probe(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                                             size_t n) {
     const size_t step = size_t(gridDim.x) * kProbeThreads * kProbeUnroll;
     for (size_t base = size_t(blockIdx.x) * kProbeThreads * kProbeUnroll + threadIdx.x; base < n; base += step) {
@@ -73,18 +75,19 @@ __device__ __forceinline__ bool vis_coords(const double* __restrict__ uvw, long 
         w = -w;
     }
     if (w > P.wmax) return false;
-    double up = __dmul_rn(P.umul, u), vp = __dmul_rn(P.umul, v), wp = __dmul_rn(P.nscale, w);
+    double up = __dmul_rn(P.umul, u), vp = __dmul_rn(P.umul, v), wp = __dadd_rn(__dmul_rn(P.nscale, w), P.wshift);
     if (fabs(up) > 1e15 || fabs(vp) > 1e15) return false;
     long long fu, fv, ft;
     axis_support(up, P.W, c.nu_u, fu);
     axis_support(vp, P.W, c.nu_v, fv);
-    axis_support(wp, P.W, c.nu_w, ft);
-    // N' is a power of two: the mask is the non-negative residue modulo N'
-    const long long mask = P.Np - 1;
-    c.ru = int(fu & mask);
-    c.rv = int(fv & mask);
+    axis_support(wp, P.Wz, c.nu_w, ft);
+    // the non-negative residues modulo N'
+    long long ru = fu % P.Np, rv = fv % P.Np;
+    c.ru = int(ru < 0 ? ru + P.Np : ru);
+    c.rv = int(rv < 0 ? rv + P.Np : rv);
     long long it = ft - P.t_lo;
-    if (it < 0 || it > P.n_layers - P.W) return false;
+    if (P.tclamp && it == P.n_layers) it = P.n_layers - 1;      // w = wmax: the last bin is closed
+    if (it < 0 || it > P.n_layers - P.Wz) return false;
     c.rt = int(it) + ch * P.nbt * kTileT;
     c.w = w;
     return true;
@@ -156,7 +159,7 @@ __device__ __forceinline__ int agg_slot(AggTable& T, int key) {
     return -1;
 }
 
-__global__ void __launch_bounds__(kAggThreads) k_bin_count(const double* __restrict__ uvw,
+static __global__ void __launch_bounds__(kAggThreads) k_bin_count(const double* __restrict__ uvw,
                                                            const long long* __restrict__ coff,
                                                            const int* __restrict__ cblk, DevParams P,
                                                            uint32_t* __restrict__ count,
@@ -209,7 +212,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
     return woff + inc - x;
 }
 
-__global__ void k_scan_local(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int n,
+static __global__ void k_scan_local(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int n,
                              uint32_t* __restrict__ block_sums) {
     __shared__ uint32_t sh[16];
     const int base = blockIdx.x * 1024 + threadIdx.x * 4;
@@ -230,7 +233,7 @@ __global__ void k_scan_local(const uint32_t* __restrict__ in, uint32_t* __restri
 }
 
 // single block of 1024 threads; each thread scans ceil(nb / 1024) consecutive sums
-__global__ void k_scan_sums(uint32_t* __restrict__ block_sums, int nb, uint32_t* __restrict__ grand) {
+static __global__ void k_scan_sums(uint32_t* __restrict__ block_sums, int nb, uint32_t* __restrict__ grand) {
     __shared__ uint32_t sh[16];
     const int per = (nb + 1023) / 1024;
     const int base = threadIdx.x * per;
@@ -249,7 +252,7 @@ __global__ void k_scan_sums(uint32_t* __restrict__ block_sums, int nb, uint32_t*
     if (threadIdx.x == 0) *grand = total;
 }
 
-__global__ void k_scan_add(uint32_t* __restrict__ out, int n, const uint32_t* __restrict__ block_sums) {
+static __global__ void k_scan_add(uint32_t* __restrict__ out, int n, const uint32_t* __restrict__ block_sums) {
     const int base = blockIdx.x * 1024 + threadIdx.x * 4;
     const uint32_t add = block_sums[blockIdx.x];
 #pragma unroll
@@ -333,17 +336,19 @@ __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __res
 // are ordered by (layer, u, v) of their first support index, so that records
 // with the same support box are adjacent (long runs along Earth-rotation
 // tracks).
+// With separate widths, the layer axis uses Bt = 17 - W_z and the u, v axes
+// Buv = 17 - W.
 __device__ __forceinline__ int class_part(int hi, int B) { return hi ? kTileT - B : B; }
 __device__ __forceinline__ int class_position(int c) { return c ^ (c >> 1) ^ (c >> 2); }   // inverse Gray code
-__device__ __forceinline__ int class_of(int lt, int lr, int ls, int B) {
-    return int(lt >= B) | (int(lr >= B) << 1) | (int(ls >= B) << 2);
+__device__ __forceinline__ int class_of(int lt, int lr, int ls, int Bt, int Buv) {
+    return int(lt >= Bt) | (int(lr >= Buv) << 1) | (int(ls >= Buv) << 2);
 }
 // rank of the first key of class position q (q = 0..8) among the 4096 keys
-__device__ __forceinline__ int class_base(int q, int B) {
+__device__ __forceinline__ int class_base(int q, int Bt, int Buv) {
     int b = 0;
     for (int k = 0; k < q; ++k) {
         const int c = k ^ (k >> 1);
-        b += class_part(c & 1, B) * class_part(c & 2, B) * class_part(c & 4, B);
+        b += class_part(c & 1, Bt) * class_part(c & 2, Buv) * class_part(c & 4, Buv);
     }
     return b;
 }
@@ -365,16 +370,16 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
     if (b1 == b0) return;
     const int br = bin % P.nbr, bs = (bin / P.nbr) % P.nbs, bt = bin / (P.nbr * P.nbs);
     const int tid = threadIdx.x;
-    const int B = 17 - P.W;
-    if (tid < 9) cbase[tid] = class_base(tid, B);
+    const int Buv = 17 - P.W, Bt = 17 - P.Wz;
+    if (tid < 9) cbase[tid] = class_base(tid, Bt, Buv);
     for (int i = tid; i < NK; i += 256) hist[i] = 0u;
     __syncthreads();
     auto key_of = [&](const Rec<R>& r) {
         const int lr = int(r.ruv & 0xffffu) - br * kTileR, ls = int(r.ruv >> 16) - bs * kTileS;
         const int lt = int(r.rt) - bt * kTileT;
-        const int c = class_of(lt, lr, ls, B);
-        const int it = (c & 1) ? lt - B : lt, ir = (c & 2) ? lr - B : lr, is = (c & 4) ? ls - B : ls;
-        return cbase[class_position(c)] + (it * class_part(c & 2, B) + ir) * class_part(c & 4, B) + is;
+        const int c = class_of(lt, lr, ls, Bt, Buv);
+        const int it = (c & 1) ? lt - Bt : lt, ir = (c & 2) ? lr - Buv : lr, is = (c & 4) ? ls - Buv : ls;
+        return cbase[class_position(c)] + (it * class_part(c & 2, Buv) + ir) * class_part(c & 4, Buv) + is;
     };
     for (uint32_t i = b0 + tid; i < b1; i += 256) atomicAdd(&hist[key_of(in[i])], 1u);
     __syncthreads();
@@ -408,7 +413,7 @@ __global__ void __launch_bounds__(256) k_bin_local_sort(const Rec<R>* __restrict
 // (degrid); the FFT passes treat unmarked tiles as zero (grid) or skip them
 // (degrid).  A row of tiles (t tile, u tile) is marked in `rows` when one of
 // its tiles is (`rows` zero on entry; racing stores all write 1).
-__global__ void k_tile_occupancy(const uint32_t* __restrict__ start, const uint32_t* __restrict__ cls, DevParams P,
+static __global__ void k_tile_occupancy(const uint32_t* __restrict__ start, const uint32_t* __restrict__ cls, DevParams P,
                                  uint8_t* __restrict__ occ, uint8_t* __restrict__ rows, uint32_t* __restrict__ flag) {
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
     const int nt = P.nch * P.nbt * P.nbs * P.nbr;
@@ -439,7 +444,7 @@ __global__ void k_tile_occupancy(const uint32_t* __restrict__ start, const uint3
 
 // The occupied tiles in tile order: list[pos[t]] = t for every marked tile t,
 // pos the exclusive scan of the flags (pos[n] = number of marked tiles).
-__global__ void k_tile_list(const uint8_t* __restrict__ occ, const uint32_t* __restrict__ pos, int n,
+static __global__ void k_tile_list(const uint8_t* __restrict__ occ, const uint32_t* __restrict__ pos, int n,
                             uint32_t* __restrict__ list) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n && occ[t]) list[pos[t]] = uint32_t(t);
@@ -550,27 +555,29 @@ __device__ __forceinline__ int tile_of_block(const DevParams& P, const uint32_t*
     return int(tlist[first + xcd_interleave<4>(blockIdx.x, cnt)]);
 }
 
-// Kernel weights of one record on the three axes by Horner's rule; the same
-// least-misfit function on every axis, so each coefficient read (an LDS
-// broadcast) feeds three chains.
-template <typename R, int W>
-__device__ __forceinline__ void record_weights(const Rec<R>& r, const R* __restrict__ coef, R (&wu)[W], R (&wv)[W],
-                                               R (&wt)[W]) {
+// Kernel weights of one record on the three axes by Horner's rule: u and v
+// from coef (width W), the layer axis from coefz (width WZ).  SAME: the w-axis
+// design is the u, v one (WZ == W), so each coefficient read feeds three chains.
+template <typename R, int W, int WZ, bool SAME>
+__device__ __forceinline__ void record_weights(const Rec<R>& r, const R* __restrict__ coef, const R* __restrict__ coefz,
+                                               R (&wu)[W], R (&wv)[W], R (&wt)[WZ]) {
     constexpr int D = KernelDegree<R>::value;
+    static_assert(!SAME || WZ == W, "one design on all axes needs equal widths");
 #pragma unroll
     for (int a = 0; a < W; ++a) {
         const R* c = coef + a * (D + 1);
-        R hu = c[D], hv = c[D], ht = c[D];
+        const R* cz = (SAME ? coef : coefz) + (a < WZ ? a : 0) * (D + 1);
+        R hu = c[D], hv = c[D], ht = cz[D];
 #pragma unroll
         for (int k = D - 1; k >= 0; --k) {
             const R ck = c[k];
             hu = hu * r.nu[0] + ck;
             hv = hv * r.nu[1] + ck;
-            ht = ht * r.nu[2] + ck;
+            ht = ht * r.nu[2] + (SAME ? ck : cz[k]);
         }
         wu[a] = hu;
         wv[a] = hv;
-        wt[a] = ht;
+        if (a < WZ) wt[a] = ht;
     }
 }
 
@@ -587,10 +594,10 @@ __device__ __forceinline__ int word_bits(float v) { return __float_as_int(v); }
 __device__ __forceinline__ int word_bits(double v) { return __double2loint(v); }
 
 // Scatter: residue classes (Romein 2012, extended to three axes).  Lane (x, y)
-// owns, among the W x W x W support cells of a record, the W cells whose u and
-// v indices are congruent to x and y modulo W, one per layer residue a: for
+// owns, among the W x W x WZ support cells of a record, the WZ cells whose u
+// and v indices are congruent to x and y modulo W, one per layer residue a: for
 // support start (dr, ds, dt) the u-cell dr + ((x - dr) mod W), the v-cell
-// ds + ((y - ds) mod W) and the layer dt + ((a - dt) mod W).  Each round a wave
+// ds + ((y - ds) mod W) and the layer dt + ((a - dt) mod WZ).  Each round a wave
 // stages 16 or 32 records into its slots (four or two lanes per record): the u
 // weights times the value and the v weights rotated by the support start (so lane x reads position x
 // whatever the record), and the layer weights rotated by dt with the packed
@@ -600,7 +607,7 @@ __device__ __forceinline__ int word_bits(double v) { return __double2loint(v); }
 // (atomics: the four waves share it) and restart from zero.  Records are sorted
 // by support start inside each touch class, so supports mostly coincide or
 // move by one cell.
-template <typename R, int W>
+template <typename R, int W, int WZ>
 struct ScatterCfg {
     // records per wave round: 16 (four lanes stage each) for W <= 7, where the
     // block then fits in 40 KB of LDS (FP32: four blocks per CU) or 80 KB
@@ -615,29 +622,30 @@ struct ScatterCfg {
     static constexpr int kPairs = W * W;
     static constexpr int kPI = (kPairs + 63) / 64;                // (x, y) residue pairs per lane
     static constexpr int kCells = kTileT * kTileR * kTileS;
-    static constexpr int kWords = (W * sizeof(R) + 15) / 16 * 16 / sizeof(R);   // 16-byte rows
+    static constexpr int kWords = (WZ * sizeof(R) + 15) / 16 * 16 / sizeof(R);   // 16-byte rows
 };
 
-template <typename R, int W>
+template <typename R, int W, int WZ>
 struct __align__(16) ScatterStage {
-    // layer weights rotated (position (a + dt) mod W holds C(s_a - nu_w))
-    R words[ScatterCfg<R, W>::kSlots][ScatterCfg<R, W>::kWords];
+    // layer weights rotated (position (a + dt) mod WZ holds C_z(s_a - nu_w))
+    R words[ScatterCfg<R, W, WZ>::kSlots][ScatterCfg<R, W, WZ>::kWords];
     // value times u weights (real, imaginary), rotated by dr; v weights rotated by ds
-    R wuv[ScatterCfg<R, W>::kSlots][3 * W];
+    R wuv[ScatterCfg<R, W, WZ>::kSlots][3 * W];
 };
 
-template <typename R, int W>
-__global__ void __launch_bounds__((ScatterCfg<R, W>::kThreads)) k_grid_tiles(const Rec<R>* __restrict__ rec,
+template <typename R, int W, int WZ, bool SAME>
+__global__ void __launch_bounds__((ScatterCfg<R, W, WZ>::kThreads)) k_grid_tiles(const Rec<R>* __restrict__ rec,
                                                     const uint32_t* __restrict__ start,
                                                     const uint32_t* __restrict__ cls,
                                                     const uint32_t* __restrict__ tlist,
                                                     const uint32_t* __restrict__ tpos, DevParams P,
-                                                    const R* __restrict__ coef_g, cpx<R>* __restrict__ stack) {
-    using Cfg = ScatterCfg<R, W>;
+                                                    const R* __restrict__ coef_g, const R* __restrict__ coefz_g,
+                                                    cpx<R>* __restrict__ stack) {
+    using Cfg = ScatterCfg<R, W, WZ>;
     constexpr int PI = Cfg::kPI, WB = Cfg::kWaveBatch, D = KernelDegree<R>::value;
     __shared__ R tre[Cfg::kCells];
     __shared__ R tim[Cfg::kCells];
-    __shared__ ScatterStage<R, W> st;
+    __shared__ ScatterStage<R, W, WZ> st;
     __shared__ TileSegs sg;
 
     const int tile = tile_of_block(P, tlist, tpos);
@@ -671,14 +679,14 @@ __global__ void __launch_bounds__((ScatterCfg<R, W>::kThreads)) k_grid_tiles(con
             py[i] = pc % W;
             cr[i] = cs[i] = -1000;
         }
-        int ct[W];                                   // owned layer per residue (wave-uniform)
-        R ax[PI][W], ay[PI][W];
+        int ct[WZ];                                  // owned layer per residue (wave-uniform)
+        R ax[PI][WZ], ay[PI][WZ];
 #pragma unroll
-        for (int a = 0; a < W; ++a) ct[a] = -1000;
+        for (int a = 0; a < WZ; ++a) ct[a] = -1000;
 #pragma unroll
         for (int i = 0; i < PI; ++i)
 #pragma unroll
-            for (int a = 0; a < W; ++a) ax[i][a] = ay[i][a] = R(0);
+            for (int a = 0; a < WZ; ++a) ax[i][a] = ay[i][a] = R(0);
         // add sum (i, a) to its owned cell if that cell is in the tile
         auto add_cell = [&](int i, int a) {
             const int t = ct[a];
@@ -704,18 +712,18 @@ __global__ void __launch_bounds__((ScatterCfg<R, W>::kThreads)) k_grid_tiles(con
                 const int nr = dr + xr, ns = ds + ys;
                 if (nr != cr[i] || ns != cs[i]) {
 #pragma unroll
-                    for (int a = 0; a < W; ++a) add_cell(i, a);
+                    for (int a = 0; a < WZ; ++a) add_cell(i, a);
                     cr[i] = nr;
                     cs[i] = ns;
                 }
             }
             if (dt != prev_dt) {
                 prev_dt = dt;
-                const int mt = mod_w<W>(-dt);
+                const int mt = mod_w<WZ>(-dt);
 #pragma unroll
-                for (int a = 0; a < W; ++a) {
+                for (int a = 0; a < WZ; ++a) {
                     int k = a + mt;
-                    k -= k >= W ? W : 0;
+                    k -= k >= WZ ? WZ : 0;
                     const int nt = dt + k;
                     if (nt != ct[a]) {
 #pragma unroll
@@ -734,6 +742,7 @@ __global__ void __launch_bounds__((ScatterCfg<R, W>::kThreads)) k_grid_tiles(con
         constexpr int LPR = Cfg::kLanesPerRecord;
         static_assert(WB * LPR == 64, "the wave stages WB records with LPR lanes each");
         constexpr int A0 = (W + LPR - 1) / LPR;
+        static_assert(WZ <= W, "the w-axis function is at most as wide as the u, v one");
         const int rl = lane & (WB - 1), half = lane / WB;
         // the lane's next record: virtual position vn in range g (ranges only
         // move forward as vn grows by WB per round)
@@ -750,28 +759,32 @@ __global__ void __launch_bounds__((ScatterCfg<R, W>::kThreads)) k_grid_tiles(con
             const int d = (dr + 128) | ((ds + 128) << 8) | ((dt + 128) << 16);
             if (rl < n) {
                 // stage: rotated weights, value folded into the u weights
-                const int pr = mod_w<W>(dr), ps = mod_w<W>(ds), pt = mod_w<W>(dt);
+                const int pr = mod_w<W>(dr), ps = mod_w<W>(ds), pt = mod_w<WZ>(dt);
                 const int slot = slot0 + rl;
 #pragma unroll
                 for (int i = 0; i < A0; ++i) {
                     const int a = i + half * A0;
                     const R* c = coef_g + min(a, W - 1) * (D + 1);
-                    R hu = c[D], hv = c[D], ht = c[D];
+                    const R* cz = (SAME ? coef_g : coefz_g) + min(a, WZ - 1) * (D + 1);
+                    R hu = c[D], hv = c[D], ht = cz[D];
 #pragma unroll
                     for (int k = D - 1; k >= 0; --k) {
                         const R ck = c[k];
                         hu = hu * nxt.nu[0] + ck;
                         hv = hv * nxt.nu[1] + ck;
-                        ht = ht * nxt.nu[2] + ck;
+                        ht = ht * nxt.nu[2] + (SAME ? ck : cz[k]);
                     }
                     if (a < W) {
-                        int ku = pr + a, kv = ps + a, kt = pt + a;
+                        int ku = pr + a, kv = ps + a;
                         ku -= ku >= W ? W : 0;
                         kv -= kv >= W ? W : 0;
-                        kt -= kt >= W ? W : 0;
                         st.wuv[slot][ku] = nxt.v[0] * hu;
                         st.wuv[slot][W + ku] = nxt.v[1] * hu;
                         st.wuv[slot][2 * W + kv] = hv;
+                    }
+                    if (a < WZ) {
+                        int kt = pt + a;
+                        kt -= kt >= WZ ? WZ : 0;
                         st.words[slot][kt] = ht;
                     }
                 }
@@ -790,11 +803,11 @@ __global__ void __launch_bounds__((ScatterCfg<R, W>::kThreads)) k_grid_tiles(con
             // group); each slot's stage values are read while the previous
             // slot's products are formed
             struct Slot {
-                R wt[W], fx[PI], fy[PI], fv[PI];
+                R wt[WZ], fx[PI], fy[PI], fv[PI];
             };
             auto read_slot = [&](int slot, Slot& q) {
 #pragma unroll
-                for (int a = 0; a < W; ++a) q.wt[a] = st.words[slot][a];       // broadcast
+                for (int a = 0; a < WZ; ++a) q.wt[a] = st.words[slot][a];      // broadcast
 #pragma unroll
                 for (int i = 0; i < PI; ++i) {
                     q.fx[i] = st.wuv[slot][px[i]];
@@ -817,7 +830,7 @@ __global__ void __launch_bounds__((ScatterCfg<R, W>::kThreads)) k_grid_tiles(con
                     for (int i = 0; i < PI; ++i) {
                         const R gx = c.fx[i] * c.fv[i], gy = c.fy[i] * c.fv[i];
 #pragma unroll
-                        for (int a = 0; a < W; ++a) {
+                        for (int a = 0; a < WZ; ++a) {
                             ax[i][a] += gx * c.wt[a];
                             ay[i][a] += gy * c.wt[a];
                         }
@@ -829,7 +842,7 @@ __global__ void __launch_bounds__((ScatterCfg<R, W>::kThreads)) k_grid_tiles(con
 #pragma unroll
         for (int i = 0; i < PI; ++i)
 #pragma unroll
-            for (int a = 0; a < W; ++a) add_cell(i, a);
+            for (int a = 0; a < WZ; ++a) add_cell(i, a);
     }
     __syncthreads();
     // write the tile: rows of kTileS cells
@@ -859,13 +872,14 @@ struct GatherCfg {
 // At least two waves per SIMD: left alone, the FP64 instances hold a layer's
 // cell loads in flight in 320 registers (one wave per SIMD); at two waves they
 // spill a little and run 1.5x faster (FP32 is at four waves either way).
-template <typename R, int W>
+template <typename R, int W, int WZ, bool SAME>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_degrid_tiles(const Rec<R>* __restrict__ rec,
                                                       const uint32_t* __restrict__ start,
                                                       const uint32_t* __restrict__ cls,
                                                       const uint32_t* __restrict__ tlist,
                                                       const uint32_t* __restrict__ tpos, DevParams P,
                                                       const R* __restrict__ coef_g,
+                                                      const R* __restrict__ coefz_g,
                                                       const cpx<R>* __restrict__ stack, cpx<R>* __restrict__ part,
                                                       size_t part_stride) {
     using G = GatherCfg<R, W>;
@@ -873,6 +887,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     constexpr int WB = 64;
     __shared__ cpx<R> g[G::kLen];
     __shared__ R coef[W * (D + 1)];
+    __shared__ R coefz[SAME ? 1 : WZ * (D + 1)];
     __shared__ TileSegs sg;
 
     const int tile = tile_of_block(P, tlist, tpos);
@@ -885,6 +900,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 
     if (tid < 64) tile_segments(start, cls, P, bt, bs, br, sg);
     for (int i = tid; i < W * (D + 1); i += 256) coef[i] = coef_g[i];
+    if (!SAME)
+        for (int i = tid; i < WZ * (D + 1); i += 256) coefz[i] = coefz_g[i];
     __syncthreads();
     const int nseg = sg.n;
     const uint32_t total = sg.off[nseg];
@@ -927,18 +944,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const int dr = wrap_offset(int(r.ruv & 0xffffu), r0, P.Np);
         const int ds = wrap_offset(int(r.ruv >> 16), s0, P.Np);
         const int dt = int(r.rt) - t0;
-        R wu[W], wv_[W], wt[W];
-        record_weights<R, W>(r, coef, wu, wv_, wt);
+        R wu[W], wv_[W], wt[WZ];
+        record_weights<R, W, WZ, SAME>(r, coef, coefz, wu, wv_, wt);
 #pragma unroll
         for (int a = 0; a < W; ++a) {
             wu[a] = unsigned(dr + a) < unsigned(kTileR) ? wu[a] : R(0);
             wv_[a] = unsigned(ds + a) < unsigned(kTileS) ? wv_[a] : R(0);
-            wt[a] = unsigned(dt + a) < unsigned(nt_valid) ? wt[a] : R(0);
         }
+#pragma unroll
+        for (int a = 0; a < WZ; ++a) wt[a] = unsigned(dt + a) < unsigned(nt_valid) ? wt[a] : R(0);
         const cpx<R>* row = g + (G::kGuard + dr * G::kLR + ds);
         R sx = R(0), sy = R(0);
 #pragma unroll
-        for (int a = 0; a < W; ++a) {
+        for (int a = 0; a < WZ; ++a) {
             const int tt = min(max(dt + a, 0), kTileT - 1);
             const cpx<R>* pa = row + tt * G::kLT;
             R ax = R(0), ay = R(0);
@@ -969,14 +987,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // for a folded visibility, stored to its visibility.
 template <typename R>
 __global__ void k_degrid_finish(const Rec<R>* __restrict__ rec, const uint32_t* __restrict__ n_rec,
-                                const cpx<R>* __restrict__ part, size_t part_stride, int W,
+                                const cpx<R>* __restrict__ part, size_t part_stride, int W, int Wz,
                                 cpx<R>* __restrict__ vis) {
     const size_t p = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= *n_rec) return;
     const Rec<R> r = rec[p];
-    const int B = 17 - W;
     const int c = class_of(int(r.rt) & (kTileT - 1), int(r.ruv & 0xffffu) & (kTileR - 1),
-                           int(r.ruv >> 16) & (kTileS - 1), B);
+                           int(r.ruv >> 16) & (kTileS - 1), 17 - Wz, 17 - W);
     R sx = R(0), sy = R(0);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -1001,20 +1018,24 @@ __global__ void k_degrid_finish(const Rec<R>* __restrict__ rec, const uint32_t* 
 // (Algorithm 5 step 3c); the degrid input places image index p at bin
 // (p - N/2) mod N' (zero padding, Algorithm 6 step 3b).
 
-template <typename R, int LOGN>
+template <typename R, int NP>
 struct FftCfg {
-    static constexpr int N = 1 << LOGN;
+    static constexpr int N = NP;
     static constexpr int T = N / 16;
-    static constexpr int kLineBytes = LinePad<N>::size * int(sizeof(cpx<R>));
-    // lines per block for the transposed passes: as many as fit in half the LDS,
-    // so that two blocks share a CU and overlap their load and transform phases
-    static constexpr int kNLt0 = (80 * 1024 - 2048) / kLineBytes;
-    static constexpr int kNLt1 = kNLt0 < 1 ? 1 : kNLt0;
-    static constexpr int kNLt2 = kNLt1 >= 16 ? 16 : kNLt1 >= 8 ? 8 : kNLt1 >= 4 ? 4 : kNLt1 >= 2 ? 2 : 1;
-    // lines per block for the row passes: at least 256 threads
+    // lines per block for the row passes: at least ~256 threads
     static constexpr int kNLr = (T >= 256) ? 1 : 256 / T;
-    static constexpr int kNLt = kNLr < 16 ? kNLr : 16;
+    // lines per block for the tile-row passes: a power of two dividing the 16
+    // rows of a row of tiles
+    static constexpr int kNLt = kNLr >= 16 ? 16 : kNLr >= 8 ? 8 : kNLr >= 4 ? 4 : kNLr >= 2 ? 2 : 1;
 };
+
+// (f + N/2) mod N' for a bin f < N' (image index of FFT bin f, or the bin of
+// image index f)
+template <int NP>
+__device__ __forceinline__ int shift_half(int f, int half) {
+    const int q = f + half;
+    return q >= NP ? q - NP : q;
+}
 
 // grid pass A: IFFT along s of stack rows [t][r][:], keep image rows q, write
 // the lines [t][r][q] (transposed afterwards by k_transpose).  One block per
@@ -1024,11 +1045,11 @@ struct FftCfg {
 // written (its lines are zero).  Layer t of the pass is virtual layer
 // t + t_base; in a batched call (chl = the channels' layer stride, else 0) a
 // padding layer (virtual layer mod chl >= n_layers) is skipped.
-template <typename R, int LOGN>
-__global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
+template <typename R, int NP>
+__global__ void __launch_bounds__((FftCfg<R, NP>::kNLt * FftCfg<R, NP>::T))
     k_grid_fft_a(const cpx<R>* __restrict__ stack, const uint8_t* __restrict__ occ, cpx<R>* __restrict__ inter,
                  const cpx<R>* __restrict__ tw, int N, int n_layers, int chl, int nbr, int t_base) {
-    using C = FftCfg<R, LOGN>;
+    using C = FftCfg<R, NP>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size, NG = kTileR / NL;
     static_assert(kTileR % NL == 0, "a row of tiles is a whole number of line groups");
     __shared__ cpx<R> buf[NL * LP];
@@ -1061,12 +1082,12 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
 #pragma unroll
         for (int k = 0; k < 16; ++k) v[k] = nx[k];
         if (g + 1 < NG) load(g + 1, nx);
-        fft_line<R, LOGN, +1>(v, lbuf, tw, j);
+        fft_line<R, NP, +1>(v, lbuf, tw, j);
         // bin f = j + T k holds image row q = (f + N/2) mod N', kept when below N
         cpx<R>* dst = dst0 + (size_t)(g * NL + line) * N;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const int q = (j + T * k + half) & (Np - 1);
+            const int q = shift_half<Np>(j + T * k, half);
             if (q < N) dst[q] = v[k];
         }
     }
@@ -1088,11 +1109,11 @@ __device__ __forceinline__ uint32_t live_mask(const uint8_t* __restrict__ mark, 
 // One launch covers a segment of P.pln consecutive layers of one channel: the
 // segment starts at layer seg0 of the pass's buffer and at layer tloc0 of the
 // channel; `accumulate` adds to the map instead of writing it.
-template <typename R, int LOGN>
-__global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
+template <typename R, int NP>
+__global__ void __launch_bounds__((FftCfg<R, NP>::kNLr * FftCfg<R, NP>::T))
     k_grid_fft_b(const cpx<R>* __restrict__ inter, const uint8_t* __restrict__ rows, const cpx<R>* __restrict__ tw,
                  const R* __restrict__ corr, R* __restrict__ dirty, DevParams P, int seg0, int tloc0, int accumulate) {
-    using C = FftCfg<R, LOGN>;
+    using C = FftCfg<R, NP>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLr, LP = LinePad<Np>::size;
     __shared__ cpx<R> buf[NL * LP];
     const int N = P.N, half = N / 2;
@@ -1108,7 +1129,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int f = j + T * k;
-        const int p = (f + half) & (Np - 1);
+        const int p = shift_half<Np>(f, half);
         pix[k] = (row_ok && p < N) ? p : -1;
         const double l = double(min(p, N - 1) - half) * P.dl;   // bins outside the image are not used
         const double r2 = l * l + m * m;
@@ -1130,8 +1151,8 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
         cpx<R> v[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) v[k] = (live >> k) & 1u ? src[j + T * k] : cpx<R>{R(0), R(0)};
-        fft_line<R, LOGN, +1>(v, lbuf, tw, j);
-        const double tl = double(tloc0 + t + P.t_lo);
+        fft_line<R, NP, +1>(v, lbuf, tw, j);
+        const double tl = double(tloc0 + t + P.t_lo) + P.tphase;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (pix[k] >= 0) {
@@ -1155,11 +1176,11 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 // degrid pass B': for each image row q and layer t: f h_x h_y h_z exp(-i 2 pi t z)
 // zero-padded along p, FFT along p -> intermediate [t][q][r] (Algorithm 6 steps 2-3).
 // Segments of one channel's layers as for k_grid_fft_b.
-template <typename R, int LOGN>
-__global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
+template <typename R, int NP>
+__global__ void __launch_bounds__((FftCfg<R, NP>::kNLr * FftCfg<R, NP>::T))
     k_degrid_fft_b(const R* __restrict__ image, const R* __restrict__ corr, const cpx<R>* __restrict__ tw,
                    const uint8_t* __restrict__ rows, cpx<R>* __restrict__ inter, DevParams P, int seg0, int tloc0) {
-    using C = FftCfg<R, LOGN>;
+    using C = FftCfg<R, NP>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLr, LP = LinePad<Np>::size;
     __shared__ cpx<R> buf[NL * LP];
     const int N = P.N, half = N / 2;
@@ -1174,7 +1195,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int f = j + T * k;
-        const int p = (f + half) & (Np - 1);
+        const int p = shift_half<Np>(f, half);
         const bool ok = row_ok && p < N;
         g[k] = ok ? image[(size_t)qq * N + p] * corr[(size_t)qq * N + p] : R(0);
         const double l = double(min(p, N - 1) - half) * P.dl;   // keeps z finite on padding bins
@@ -1185,7 +1206,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
     uint32_t live = 0;
     int live_layer = -1;
     for (int t = 0; t < P.pln; ++t) {
-        const double tl = double(tloc0 + t + P.t_lo);
+        const double tl = double(tloc0 + t + P.t_lo) + P.tphase;
         cpx<R> v[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -1193,7 +1214,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
             phase_turns(-tl * z[k], &s, &c);
             v[k] = cpx<R>{g[k] * c, g[k] * s};
         }
-        fft_line<R, LOGN, -1>(v, lbuf, tw, j);
+        fft_line<R, NP, -1>(v, lbuf, tw, j);
         if (row_ok) {
             // only frequencies r of rows of tiles with an occupied tile are used later
             const int tile_layer = __builtin_amdgcn_readfirstlane((P.pl0 + seg0 + t) / kTileT);
@@ -1216,11 +1237,11 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLr * FftCfg<R, LOGN>::T))
 // transformed.  Only marked tiles are stored (the gather reads no other); a row
 // of tiles with none marked is skipped.  Layers and padding layers as for
 // k_grid_fft_a.
-template <typename R, int LOGN>
-__global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
+template <typename R, int NP>
+__global__ void __launch_bounds__((FftCfg<R, NP>::kNLt * FftCfg<R, NP>::T))
     k_degrid_fft_a(const cpx<R>* __restrict__ inter, const uint8_t* __restrict__ occ, const cpx<R>* __restrict__ tw,
                    cpx<R>* __restrict__ stack, int N, int n_layers, int chl, int nbr, int t_base) {
-    using C = FftCfg<R, LOGN>;
+    using C = FftCfg<R, NP>;
     constexpr int Np = C::N, T = C::T, NL = C::kNLt, LP = LinePad<Np>::size, NG = kTileR / NL;
     static_assert(kTileR % NL == 0, "a row of tiles is a whole number of line groups");
     __shared__ cpx<R> buf[NL * LP];
@@ -1245,7 +1266,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
         const cpx<R>* src = inter + ((size_t)t * Np + (rt * kTileR + g * NL + line)) * N;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const int q = (j + T * k + half) & (Np - 1);
+            const int q = shift_half<Np>(j + T * k, half);
             v[k] = q < N ? src[q] : cpx<R>{R(0), R(0)};
         }
     };
@@ -1256,7 +1277,7 @@ __global__ void __launch_bounds__((FftCfg<R, LOGN>::kNLt * FftCfg<R, LOGN>::T))
 #pragma unroll
         for (int k = 0; k < 16; ++k) v[k] = nx[k];
         if (g + 1 < NG) load(g + 1, nx);
-        fft_line<R, LOGN, -1>(v, lbuf, tw, j);
+        fft_line<R, NP, -1>(v, lbuf, tw, j);
         cpx<R>* dst = stack + ((size_t)t * Np + (rt * kTileR + g * NL + line)) * Np;
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -1305,20 +1326,28 @@ __global__ void __launch_bounds__(THREADS) k_transpose(const cpx<R>* __restrict_
 
 // --------------------------------------------------------------- plan tables --
 //
-// Correction map corr[j][i] = h(x_i) h(y_j) h(z_ji) (Algorithm 5 step 5): h at the
-// pixel columns comes from the host, h(z) is evaluated here from the pointwise
-// optimality formula h(z) = int Re g dnu / int |g|^2 dnu over Gauss-Legendre
-// nodes nu_j, g(z, nu) = sum_a c_a(nu) exp(i 2 pi (s_a - nu) z).
-__global__ void k_corr_map(const double* __restrict__ hx, const double* __restrict__ cnodes,
-                           const double* __restrict__ nun, const double* __restrict__ wn, int n_nu, DevParams P,
-                           double* __restrict__ corr64, float* __restrict__ corr32) {
+// Correction map corr[j][i] = h(x_i) h(y_j) h_z(z_ji) (Algorithm 5 step 5): h at
+// the pixel columns comes from the host, h_z is evaluated here from the
+// pointwise optimality formula h(z) = int Re g dnu / int |g|^2 dnu over
+// Gauss-Legendre nodes nu_j, g(z, nu) = sum_a c_a(nu) exp(i 2 pi (s_a - nu) z),
+// with the w-axis design's c (width Wz); hz_one: no correction along z (the
+// original W-stacking corrects in x and y only, Algorithm 3 step 5).
+static __global__ void k_corr_map(const double* __restrict__ hx, const double* __restrict__ cnodes,
+                           const double* __restrict__ nun, const double* __restrict__ wn, int n_nu, int Wz,
+                           int hz_one, DevParams P, double* __restrict__ corr64, float* __restrict__ corr32) {
     const int N = P.N, half = N / 2;
     const int i = blockIdx.x * blockDim.x + threadIdx.x, jrow = blockIdx.y;
     if (i >= N) return;
+    if (hz_one) {
+        const double v = hx[i] * hx[jrow];
+        corr64[(size_t)jrow * N + i] = v;
+        corr32[(size_t)jrow * N + i] = float(v);
+        return;
+    }
     const double l = double(i - half) * P.dl, m = double(jrow - half) * P.dl;
     const double r2 = l * l + m * m;
     const double z = (-r2 / (1.0 + sqrt(1.0 - r2))) / P.nscale + P.zshift;
-    const int W = P.W;
+    const int W = Wz;
     double step_s, step_c;
     sincospi(2.0 * z, &step_s, &step_c);                         // exp(i 2 pi z)
     double num = 0.0, den = 0.0;

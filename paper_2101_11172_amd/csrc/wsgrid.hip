@@ -31,6 +31,7 @@
 #include "../../include/wsgrid.h"
 #include "design.hpp"
 #include "kernels.hpp"
+#include "launch.hpp"
 
 using namespace wsg;
 
@@ -87,34 +88,37 @@ struct StageEvent {
 thread_local bool g_timing = false;
 thread_local std::vector<StageEvent> g_events;
 
-struct StageMark {
-    hipStream_t s;
-    int stage;
-    hipEvent_t a = nullptr;
-    StageMark(hipStream_t s_, int st) : s(s_), stage(st) {
-        static_assert(WSG_NSTAGES == 10, "stage ids are listed in wsgrid.h");
-        if (g_timing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
-    }
-    ~StageMark() {
-        if (!a) return;
-        hipEvent_t b = nullptr;
-        if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess)
-            g_events.push_back({stage, a, b});
-        else
-            (void)hipEventDestroy(a);
-    }
-};
-
 }  // namespace
+
+namespace wsg {
+
+StageMark::StageMark(hipStream_t s_, int st) : s(s_), stage(st) {
+    static_assert(WSG_NSTAGES == 10, "stage ids are listed in wsgrid.h");
+    if (g_timing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+}
+
+StageMark::~StageMark() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess)
+        g_events.push_back({stage, a, b});
+    else
+        (void)hipEventDestroy(a);
+}
+
+}  // namespace wsg
 
 struct wsg_plan {
     PlanParams pp;
-    KernelDesign kd;
+    KernelDesign kd;        // u, v (and w when same_design)
+    KernelDesign kdz;       // w axis: its own least-misfit design, or the top hat
+    bool same_design = true;
     int device = -1;
-    int log2_np = 0;
     int nbr = 0, nbs = 0, nbt = 0;
     double* poly64 = nullptr;
     float* poly32 = nullptr;
+    double* polyz64 = nullptr;     // w-axis coefficients (same_design: poly64 again)
+    float* polyz32 = nullptr;
     double* corr64 = nullptr;
     float* corr32 = nullptr;
     cpx<double>* tw64 = nullptr;
@@ -192,6 +196,10 @@ DevParams dev_params(const wsg_plan* p) {
     P.N = p->pp.N;
     P.Np = p->pp.Nprime;
     P.W = p->pp.W;
+    P.Wz = p->pp.Wz;
+    P.tclamp = p->pp.method == kOriginal ? 1 : 0;
+    P.wshift = p->pp.w_shift;
+    P.tphase = p->pp.t_phase;
     P.n_layers = p->pp.n_layers();
     P.t_lo = p->pp.t_lo;
     P.nbr = p->nbr;
@@ -220,126 +228,6 @@ void scan(const uint32_t* count, uint32_t* start, uint32_t* bsums, int n, hipStr
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, count, start, n, bsums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb, start + n);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, s, start, n, (const uint32_t*)bsums);
-}
-
-// ---- compile-time dispatch over W and log2 N' ----
-
-template <typename R, int W>
-void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
-                    const uint32_t* tlist, const uint32_t* tpos, const DevParams& P, const R* coef, cpx<R>* stack,
-                    cpx<R>* part, size_t part_stride, hipStream_t s) {
-    if (grid)
-        hipLaunchKernelGGL((k_grid_tiles<R, W>), dim3(nblocks), dim3(ScatterCfg<R, W>::kThreads), 0, s, rec, start,
-                           cls, tlist, tpos, P,
-                           coef, stack);
-    else
-        hipLaunchKernelGGL((k_degrid_tiles<R, W>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, tlist, tpos, P,
-                           coef,
-                           (const cpx<R>*)stack, part, part_stride);
-}
-
-template <typename R>
-void launch_tiles(bool grid, int W, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
-                  const uint32_t* tlist, const uint32_t* tpos, const DevParams& P, const R* coef, cpx<R>* stack,
-                  cpx<R>* part, size_t part_stride, hipStream_t s) {
-    switch (W) {
-#define WSG_W(w) \
-    case w:                                                                                                      \
-        launch_tiles_w<R, w>(grid, nblocks, rec, start, cls, tlist, tpos, P, coef, stack, part, part_stride, s); \
-        break;
-        WSG_W(1) WSG_W(2) WSG_W(3) WSG_W(4) WSG_W(5) WSG_W(6) WSG_W(7) WSG_W(8)
-        WSG_W(9) WSG_W(10) WSG_W(11) WSG_W(12) WSG_W(13) WSG_W(14) WSG_W(15) WSG_W(16)
-#undef WSG_W
-        default: break;
-    }
-}
-
-// r_in: the stack frequency r is the input row index (grid), else the output's.
-// 512 threads per 64 x 64 tile (8 elements each) measured fastest (256: 1.45 ms,
-// 512: 1.04 ms, 1024: 1.18 ms per wide-field transpose).
-template <typename R>
-void transpose(const DevParams& P, const cpx<R>* in, cpx<R>* out, int A, int B, bool r_in, const uint8_t* rows,
-               hipStream_t s) {
-    constexpr int TH = 512;
-    const unsigned blocks = unsigned(P.pln) * unsigned((A + 63) / 64) * unsigned((B + 63) / 64);
-    const int chl = P.nch > 1 ? P.nbt * kTileT : 0;     // 0: one channel, no padding layers to skip
-    if (r_in)
-        hipLaunchKernelGGL((k_transpose<R, TH, true>), dim3(blocks), dim3(TH), 0, s, in, out, A, B, rows, P.nbr,
-                           P.pl0, chl, P.n_layers);
-    else
-        hipLaunchKernelGGL((k_transpose<R, TH, false>), dim3(blocks), dim3(TH), 0, s, in, out, A, B, rows, P.nbr,
-                           P.pl0, chl, P.n_layers);
-}
-
-// One layer pass of the FFT stages.  Pass B (along u / p, with the w-screen)
-// runs once per channel segment of the pass: the virtual layers of channel c
-// in the pass, whose map is dirty + c N^2 (grid, written by the channel's first
-// segment and added to by later ones) or image + c N^2 (degrid).
-template <typename R, int LOGN>
-void launch_fft_n(bool grid, const DevParams& P, const uint8_t* occ, const uint8_t* rows, cpx<R>* stack, cpx<R>* inter,
-                  cpx<R>* inter2, const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
-    using C = FftCfg<R, LOGN>;
-    const unsigned grid_a = unsigned(P.pln) * unsigned(C::N / kTileR);
-    const unsigned grid_b = unsigned((P.N + C::kNLr - 1) / C::kNLr);
-    const int chl = P.nbt * kTileT;
-    const size_t map = size_t(P.N) * size_t(P.N);
-    auto segments = [&](auto&& fn) {
-        for (int c = P.pl0 / chl; c < P.nch && c * chl < P.pl0 + P.pln; ++c) {
-            const int lo = std::max(P.pl0, c * chl), hi = std::min(P.pl0 + P.pln, c * chl + P.n_layers);
-            if (hi > lo) fn(c, lo, hi);
-        }
-    };
-    if (grid) {
-        {
-            StageMark mark(s, 2);
-            hipLaunchKernelGGL((k_grid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
-                               (const cpx<R>*)stack, occ, inter, tw, P.N, P.n_layers, P.nch > 1 ? chl : 0, P.nbr,
-                               P.pl0);
-        }
-        {
-            StageMark mark(s, 8);
-            transpose<R>(P, inter, inter2, P.Np, P.N, true, rows, s);     // [t][r][q] -> [t][q][r]
-        }
-        StageMark mark(s, 3);
-        segments([&](int c, int lo, int hi) {
-            DevParams Q = P;
-            Q.pln = hi - lo;
-            hipLaunchKernelGGL((k_grid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
-                               (const cpx<R>*)inter2, rows, tw, corr, dirty + size_t(c) * map, Q, lo - P.pl0,
-                               lo - c * chl, lo > c * chl ? 1 : 0);
-        });
-    } else {
-        {
-            StageMark mark(s, 5);
-            segments([&](int c, int lo, int hi) {
-                DevParams Q = P;
-                Q.pln = hi - lo;
-                hipLaunchKernelGGL((k_degrid_fft_b<R, LOGN>), dim3(grid_b), dim3(C::kNLr * C::T), 0, s,
-                                   image + size_t(c) * map, corr, tw, rows, inter, Q, lo - P.pl0, lo - c * chl);
-            });
-        }
-        {
-            StageMark mark(s, 9);
-            transpose<R>(P, inter, inter2, P.N, P.Np, false, rows, s);    // [t][q][r] -> [t][r][q]
-        }
-        StageMark mark(s, 6);
-        hipLaunchKernelGGL((k_degrid_fft_a<R, LOGN>), dim3(grid_a), dim3(C::kNLt * C::T), 0, s,
-                           (const cpx<R>*)inter2, occ, tw, stack, P.N, P.n_layers, P.nch > 1 ? chl : 0, P.nbr,
-                           P.pl0);
-    }
-}
-
-template <typename R>
-void launch_fft(bool grid, int log2n, const DevParams& P, const uint8_t* occ, const uint8_t* rows, cpx<R>* stack,
-                cpx<R>* inter,
-                cpx<R>* inter2, const cpx<R>* tw, const R* corr, const R* image, R* dirty, hipStream_t s) {
-    switch (log2n) {
-#define WSG_N(n) \
-    case n: launch_fft_n<R, n>(grid, P, occ, rows, stack, inter, inter2, tw, corr, image, dirty, s); break;
-        WSG_N(6) WSG_N(7) WSG_N(8) WSG_N(9) WSG_N(10) WSG_N(11) WSG_N(12) WSG_N(13)
-#undef WSG_N
-        default: break;
-    }
 }
 
 __global__ void k_set_chan(ChanArgs ca, int nch, long long* __restrict__ coff, int* __restrict__ cblk) {
@@ -409,6 +297,7 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
     auto* skipped = reinterpret_cast<uint32_t*>(w + L.skipped);
     const bool f64 = sizeof(R) == 8;
     const R* coef = f64 ? reinterpret_cast<const R*>(plan->poly64) : reinterpret_cast<const R*>(plan->poly32);
+    const R* coefz = f64 ? reinterpret_cast<const R*>(plan->polyz64) : reinterpret_cast<const R*>(plan->polyz32);
     const R* corr = f64 ? reinterpret_cast<const R*>(plan->corr64) : reinterpret_cast<const R*>(plan->corr32);
     const cpx<R>* tw = f64 ? reinterpret_cast<const cpx<R>*>(plan->tw64) : reinterpret_cast<const cpx<R>*>(plan->tw32);
 
@@ -467,16 +356,18 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
         if (grid) {
             {
                 StageMark mark(s, 1);
-                launch_tiles<R>(true, P.W, nblocks, rec, start, cls, tlist, tpos, Q, coef, stack, nullptr, 0, s);
+                launch_tiles<R>(true, P.W, P.Wz, plan->same_design, nblocks, rec, start, cls, tlist, tpos, Q, coef,
+                                coefz, stack, nullptr, 0, s);
             }
-            launch_fft<R>(true, plan->log2_np, Q, occ, rows, stack, inter, inter2, tw, corr, nullptr,
+            launch_fft<R>(true, Q, occ, rows, stack, inter, inter2, tw, corr, nullptr,
                           static_cast<R*>(out), s);
         } else {
-            launch_fft<R>(false, plan->log2_np, Q, occ, rows, stack, inter, inter2, tw, corr,
+            launch_fft<R>(false, Q, occ, rows, stack, inter, inter2, tw, corr,
                           static_cast<const R*>(in), nullptr, s);
             if (M > 0) {
                 StageMark mark(s, 7);
-                launch_tiles<R>(false, P.W, nblocks, rec, start, cls, tlist, tpos, Q, coef, stack, part, size_t(M),
+                launch_tiles<R>(false, P.W, P.Wz, plan->same_design, nblocks, rec, start, cls, tlist, tpos, Q, coef,
+                                coefz, stack, part, size_t(M),
                                 s);
             }
         }
@@ -487,7 +378,7 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
         if (M > 0)
             hipLaunchKernelGGL(k_degrid_finish<R>, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s,
                                (const Rec<R>*)rec, (const uint32_t*)(start + L.nbins), (const cpx<R>*)part,
-                               size_t(M), P.W, static_cast<cpx<R>*>(out));
+                               size_t(M), P.W, P.Wz, static_cast<cpx<R>*>(out));
     }
     WSG_HIP(hipGetLastError());
     return WSG_OK;
@@ -503,14 +394,25 @@ int upload(T** dst, const T* src, size_t n) {
 int build_tables(wsg_plan* p) {
     const PlanParams& pp = p->pp;
     const KernelDesign& kd = p->kd;
+    const KernelDesign& kz = p->same_design ? p->kd : p->kdz;
     const int N = pp.N, Np = pp.Nprime;
-    if (kd.degree != KernelDegree<double>::value || kd.degree_lo != KernelDegree<float>::value)
-        return fail(WSG_EINVAL, "kernel polynomial degree mismatch between design and device code");
+    for (const KernelDesign* d : {&kd, &kz})
+        if (d->degree != KernelDegree<double>::value || d->degree_lo != KernelDegree<float>::value)
+            return fail(WSG_EINVAL, "kernel polynomial degree mismatch between design and device code");
     std::vector<double> poly64(kd.poly);
     std::vector<float> poly32(kd.poly_lo.begin(), kd.poly_lo.end());
     int rc;
     if ((rc = upload(&p->poly64, poly64.data(), poly64.size()))) return rc;
     if ((rc = upload(&p->poly32, poly32.data(), poly32.size()))) return rc;
+    if (p->same_design) {
+        p->polyz64 = p->poly64;
+        p->polyz32 = p->poly32;
+    } else {
+        std::vector<double> pz64(kz.poly);
+        std::vector<float> pz32(kz.poly_lo.begin(), kz.poly_lo.end());
+        if ((rc = upload(&p->polyz64, pz64.data(), pz64.size()))) return rc;
+        if ((rc = upload(&p->polyz32, pz32.data(), pz32.size()))) return rc;
+    }
     std::vector<cpx<double>> tw64(Np);
     std::vector<cpx<float>> tw32(Np);
     const double two_pi = 6.283185307179586476925286766559;
@@ -526,15 +428,18 @@ int build_tables(wsg_plan* p) {
     for (int i = 0; i < N; ++i) hx[i] = kd.h_at(double(i - N / 2) / double(Np));
     double *d_hx = nullptr, *d_c = nullptr, *d_nu = nullptr, *d_wn = nullptr;
     if ((rc = upload(&d_hx, hx.data(), hx.size()))) return rc;
-    if ((rc = upload(&d_c, kd.c_nodes.data(), kd.c_nodes.size()))) return rc;
-    if ((rc = upload(&d_nu, kd.nun.data(), kd.nun.size()))) return rc;
-    if ((rc = upload(&d_wn, kd.wn.data(), kd.wn.size()))) return rc;
+    // h_z from the w-axis design (the top hat of the original method: none)
+    const bool hz_one = pp.method == kOriginal;
+    const KernelDesign& kn = hz_one ? kd : kz;
+    if ((rc = upload(&d_c, kn.c_nodes.data(), kn.c_nodes.size()))) return rc;
+    if ((rc = upload(&d_nu, kn.nun.data(), kn.nun.size()))) return rc;
+    if ((rc = upload(&d_wn, kn.wn.data(), kn.wn.size()))) return rc;
     WSG_HIP(hipMalloc(reinterpret_cast<void**>(&p->corr64), size_t(N) * N * sizeof(double)));
     WSG_HIP(hipMalloc(reinterpret_cast<void**>(&p->corr32), size_t(N) * N * sizeof(float)));
     DevParams P = dev_params(p);
     hipLaunchKernelGGL(k_corr_map, dim3((N + 255) / 256, N), dim3(256), 0, 0, (const double*)d_hx,
-                       (const double*)d_c, (const double*)d_nu, (const double*)d_wn, int(kd.nun.size()), P,
-                       p->corr64, p->corr32);
+                       (const double*)d_c, (const double*)d_nu, (const double*)d_wn, int(kn.nun.size()), kn.W,
+                       hz_one ? 1 : 0, P, p->corr64, p->corr32);
     WSG_HIP(hipGetLastError());
     WSG_HIP(hipDeviceSynchronize());
     WSG_HIP(hipFree(d_hx));
@@ -551,6 +456,8 @@ void remember_call(const wsg_plan* p, const void* ws, void* stream) {
 }
 
 void free_tables(wsg_plan* p) {
+    if (p->polyz64 != p->poly64 && p->polyz64) (void)hipFree(p->polyz64);
+    if (p->polyz32 != p->poly32 && p->polyz32) (void)hipFree(p->polyz32);
     void* ptrs[] = {p->poly64, p->poly32, p->corr64, p->corr32, p->tw64, p->tw32};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -626,21 +533,31 @@ int wsg_design_eval(int W, double x0, int n_nu, const double* nu, double* c_out,
 }
 
 wsg_plan* grid_create(int N, double L, int W, double x0, double wmax) {
-    return grid_create_variant(N, L, W, x0, wmax, 1);
+    return grid_create_axes(N, L, W, x0, W, x0, wmax, WSG_IMPROVED, 0);
 }
 
 wsg_plan* grid_create_variant(int N, double L, int W, double x0, double wmax, int z_offset) {
+    return grid_create_axes(N, L, W, x0, W, x0, wmax, z_offset ? WSG_IMPROVED : WSG_IMPROVED_NO_OFFSET, 0);
+}
+
+wsg_plan* grid_create_axes(int N, double L, int W, double x0, int Wz, double z0, double wmax, wsg_method method,
+                           int n_bins) {
     wsg_plan* p = nullptr;
     try {
         PlanParams pp;
-        std::string e = make_plan_params(N, L, W, x0, wmax, &pp, z_offset != 0);
+        std::string e = make_plan_params_ext(N, L, W, x0, Wz, z0, wmax, int(method), n_bins, &pp);
         if (!e.empty()) {
             fail(WSG_EINVAL, e);
             return nullptr;
         }
-        const int Np = pp.Nprime;
-        if (Np < 64 || Np > 8192 || (Np & (Np - 1))) {
-            fail(WSG_EINVAL, "N / (2 x0) must be a power of two in [64, 8192]");
+        if (!fft_supported(pp.Nprime)) {
+            fail(WSG_EINVAL, "N / (2 x0) must be 2^a or 3 2^a in [64, 8192]");
+            return nullptr;
+        }
+        const bool same = method != WSG_ORIGINAL && Wz == W && z0 == x0;
+        if (!tiles_supported(W, Wz, same)) {
+            fail(WSG_EINVAL, "this pair of widths (W, W_z) is not compiled: W_z = W, or W = 7 with W_z <= 7, "
+                             "or W_z = 1 with W in 3 .. 8");
             return nullptr;
         }
         int dev = -1;
@@ -648,12 +565,11 @@ wsg_plan* grid_create_variant(int N, double L, int W, double x0, double wmax, in
             fail(WSG_EHIP, "no HIP device");
             return nullptr;
         }
+        const int Np = pp.Nprime;
         p = new wsg_plan();
         p->pp = pp;
         p->device = dev;
-        int lg = 0;
-        while ((1 << lg) < Np) ++lg;
-        p->log2_np = lg;
+        p->same_design = same;
         p->nbr = Np / kTileR;
         p->nbs = Np / kTileS;
         p->nbt = (pp.n_layers() + kTileT - 1) / kTileT;
@@ -663,6 +579,7 @@ wsg_plan* grid_create_variant(int N, double L, int W, double x0, double wmax, in
             return nullptr;
         }
         p->kd = design_kernel(W, x0);
+        if (!same) p->kdz = method == WSG_ORIGINAL ? top_hat_design() : design_kernel(Wz, z0);
         void* sp = nullptr;
         if (scratch_on(dev, &sp) != WSG_OK) {     // set-up: the no-alloc call's workspace on this device
             delete p;
@@ -682,6 +599,33 @@ wsg_plan* grid_create_variant(int N, double L, int W, double x0, double wmax, in
         }
         return nullptr;
     }
+}
+
+int grid_plan_axes(const wsg_plan* plan, int* W, double* x0, int* Wz, double* z0, int* method, int* n_bins,
+                   double* E_z) {
+    if (!plan) return fail(WSG_EINVAL, "null plan");
+    const PlanParams& pp = plan->pp;
+    if (W) *W = pp.W;
+    if (x0) *x0 = pp.x0;
+    if (Wz) *Wz = pp.Wz;
+    if (z0) *z0 = pp.z0;
+    if (method) *method = pp.method;
+    if (n_bins) *n_bins = pp.n_bins;
+    if (E_z) *E_z = plan->same_design ? plan->kd.E : plan->kdz.E;
+    return WSG_OK;
+}
+
+int wsg_plan_params_axes(int N, double L, int W, double x0, int Wz, double z0, double wmax, wsg_method method,
+                         int n_bins, int* Nprime, int* t_lo, int* t_hi, double* n0, double* n_scale) {
+    PlanParams pp;
+    std::string e = make_plan_params_ext(N, L, W, x0, Wz, z0, wmax, int(method), n_bins, &pp);
+    if (!e.empty()) return fail(WSG_EINVAL, e);
+    if (Nprime) *Nprime = pp.Nprime;
+    if (t_lo) *t_lo = pp.t_lo;
+    if (t_hi) *t_hi = pp.t_hi;
+    if (n0) *n0 = pp.n0;
+    if (n_scale) *n_scale = pp.n_scale;
+    return WSG_OK;
 }
 
 void grid_destroy(wsg_plan* plan) {

@@ -18,6 +18,10 @@ Workloads (all seeded with ``numpy.random.default_rng``):
   i.e. the image is Nyquist-sampled; complex N(0, 1) values (complex64 or
   complex128); W = 7, x0 = 0.25.
 * ``lowcost`` -- the ``widefield`` geometry with W = 4, x0 = 0.5.
+* ``table2`` (``table2_workload``) -- stand-in for the Table 2 simulation: a
+  512 x 512 image of a 6 degree field, 34 point sources, 27 antennas, 11
+  two-minute snapshots from -5 h to +5 h, w scaled to the field's product
+  (n_max - n_min) w_max = 7.44 of the printed layer counts.
 * ``channels`` (``channels_workload``) -- the ``widefield`` array observed in
   32 channels at f_c = 1.0 + 0.8 c / 31 GHz: uvw of the 1.4 GHz tracks scaled
   by f_c / 1.4 GHz, then all channels by one factor so that the 1.8 GHz
@@ -63,7 +67,7 @@ def uniform_uvw(M: int, umax: float, wmax: float, seed: int) -> np.ndarray:
 
 
 def array_uvw(n_ant: int, radius_m: float, lat_deg: float, dec_deg: float,
-              ha_hours: float, n_dumps: int, freq_hz: float, seed: int) -> np.ndarray:
+              ha_hours: float, n_dumps: int, freq_hz: float, seed: int, ha_offset_h: float = 0.0) -> np.ndarray:
     """Earth-rotation uvw tracks in wavelengths, time-major order [dump][baseline].
 
     Antennas uniform by area in a disc (r = R sqrt(U), theta = 2 pi U), at height
@@ -78,7 +82,7 @@ def array_uvw(n_ant: int, radius_m: float, lat_deg: float, dec_deg: float,
     dE, dN = E[jj] - E[ii], Nn[jj] - Nn[ii]
     lat, dec = np.radians(lat_deg), np.radians(dec_deg)
     X, Y, Z = -dN * np.sin(lat), dE, dN * np.cos(lat)
-    H = np.radians(15.0 * np.linspace(-ha_hours, ha_hours, n_dumps))[:, None]
+    H = np.radians(15.0 * (ha_offset_h + np.linspace(-ha_hours, ha_hours, n_dumps)))[:, None]
     sH, cH = np.sin(H), np.cos(H)
     sd, cd = np.sin(dec), np.cos(dec)
     lam = C_LIGHT / freq_hz
@@ -87,6 +91,38 @@ def array_uvw(n_ant: int, radius_m: float, lat_deg: float, dec_deg: float,
     uvw[..., 1] = (-sd * cH * X + sd * sH * Y + cd * Z) / lam
     uvw[..., 2] = (cd * cH * X - cd * sH * Y + sd * Z) / lam
     return uvw.reshape(-1, 3)
+
+
+def snapshots_uvw(n_ant: int, radius_m: float, lat_deg: float, dec_deg: float, ha_centres_h,
+                  snapshot_s: float, n_per_snapshot: int, freq_hz: float, seed: int) -> np.ndarray:
+    """Snapshot tracks: for each hour angle centre, n_per_snapshot dumps over
+    snapshot_s seconds (the same antennas and transform as array_uvw)."""
+    out = []
+    for hc in ha_centres_h:
+        one = array_uvw(n_ant, radius_m, lat_deg, dec_deg, snapshot_s / 7200.0, n_per_snapshot, freq_hz, seed,
+                        ha_offset_h=float(hc))
+        out.append(one)
+    return np.concatenate(out)
+
+
+def table2_workload(N: int = 512, seed: int = 21) -> dict:
+    """Synthetic stand-in for the paper's Table 2 simulation (a 6 degree field
+    observed on a 27-antenna array at 74 MHz, 2 minutes every hour from -5 h to
+    +5 h, 34 point sources): 27 antennas uniform in a 5.7 km-radius disc at
+    latitude 34 deg, declination 30 deg, 11 snapshots of 12 dumps; u, v scaled
+    so the N x N image of L = 2 sin(3 deg) is Nyquist-sampled, and w scaled so
+    that (n_max - n_min) w_max = 7.44, the product that reproduces Table 2's
+    printed layer counts; complex visibilities are not drawn here (the test
+    forms them from the sky)."""
+    L = 2.0 * np.sin(np.radians(3.0))
+    uvw = snapshots_uvw(27, 5700.0, 34.0, 30.0, np.arange(-5, 6), 120.0, 12, 74e6, seed)
+    uvw = uvw.copy()
+    uv_scale = 0.95 * N / (2.0 * L) / np.max(np.abs(uvw[:, :2]))
+    uvw[:, :2] *= uv_scale
+    dn = 1.0 - np.sqrt(1.0 - 2.0 * (L / 2) ** 2)
+    uvw[:, 2] *= (7.44 / dn) / np.max(np.abs(uvw[:, 2]))
+    return dict(name="table2", N=N, L=L, uvw=uvw, wmax=float(np.max(np.abs(uvw[:, 2]))),
+                sky=random_sky(N, 34, seed + 1))
 
 
 def scale_to_image(uvw: np.ndarray, N: int, L: float, fill: float = 0.95) -> np.ndarray:

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libwsgrid.so")
 HEADER = os.path.join(HERE, "..", "include", "wsgrid.h")
 
 WSG_F32, WSG_F64 = 0, 1
+WSG_IMPROVED, WSG_IMPROVED_NO_OFFSET, WSG_ORIGINAL = 0, 1, 2
+METHODS = {"improved": WSG_IMPROVED, "no_offset": WSG_IMPROVED_NO_OFFSET, "original": WSG_ORIGINAL}
 WSG_OK, WSG_EINVAL, WSG_EWORKSPACE, WSG_ENOMEM, WSG_EHIP = 0, -1, -2, -3, -4
 
 _lib = None
@@ -28,6 +30,15 @@ _SIGNATURES = {
     "grid_create": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
     "grid_create_variant": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_int]),
+    "grid_create_axes": (ctypes.c_void_p, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_int]),
+    "grid_plan_axes": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, _c_double_p, _c_int_p, _c_double_p, _c_int_p,
+                                      _c_int_p, _c_double_p]),
+    "wsg_plan_params_axes": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_int, _c_int_p, _c_int_p, _c_int_p, _c_double_p,
+                                            _c_double_p]),
     "grid_destroy": (None, [ctypes.c_void_p]),
     "grid_plan_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, _c_int_p, _c_int_p, _c_double_p, _c_double_p,
                                       _c_double_p]),
@@ -107,6 +118,31 @@ def grid_create_variant(N: int, L: float, W: int, x0: float, wmax: float, z_offs
     if not p:
         raise RuntimeError(f"grid_create_variant failed: {lib().grid_last_error().decode()}")
     return p
+
+
+def grid_create_axes(N: int, L: float, W: int, x0: float, Wz: int, z0: float, wmax: float, method: int,
+                     n_bins: int = 0) -> int:
+    p = lib().grid_create_axes(N, L, W, x0, Wz, z0, wmax, method, n_bins)
+    if not p:
+        raise RuntimeError(f"grid_create_axes failed: {lib().grid_last_error().decode()}")
+    return p
+
+
+def grid_plan_axes(plan: int) -> dict:
+    W, Wz, method, nb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    x0, z0, Ez = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _err(lib().grid_plan_axes(plan, W, x0, Wz, z0, method, nb, Ez), "grid_plan_axes")
+    return dict(W=W.value, x0=x0.value, Wz=Wz.value, z0=z0.value, method=method.value, n_bins=nb.value,
+                E_z=Ez.value)
+
+
+def wsg_plan_params_axes(N: int, L: float, W: int, x0: float, Wz: int, z0: float, wmax: float, method: int,
+                         n_bins: int = 0) -> dict:
+    Np, tlo, thi = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    n0, ns = ctypes.c_double(), ctypes.c_double()
+    _err(lib().wsg_plan_params_axes(N, L, W, x0, Wz, z0, wmax, method, n_bins, Np, tlo, thi, n0, ns),
+         "wsg_plan_params_axes")
+    return dict(Nprime=Np.value, t_lo=tlo.value, t_hi=thi.value, n0=n0.value, n_scale=ns.value)
 
 
 def grid_destroy(plan: int) -> None:
@@ -254,19 +290,26 @@ class Plan:
     max_workspace_bytes caps the workspace each precision allocates: below
     grid_workspace_bytes the library takes the w-layers in passes (at least
     grid_workspace_bytes_min is allocated).  z_offset=False selects the
-    variant without z offset (grid_create_variant).
+    variant without z offset; Wz, z0 a w-axis gridding function of its own and
+    method "improved" | "no_offset" | "original" (with n_bins, 0 for eq. N_w)
+    select grid_create_axes.
     """
 
     def __init__(self, N: int, L: float, W: int, x0: float, wmax: float, device=None,
-                 max_workspace_bytes: int | None = None, z_offset: bool = True):
+                 max_workspace_bytes: int | None = None, z_offset: bool = True, Wz: int | None = None,
+                 z0: float | None = None, method: str | None = None, n_bins: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("wsgrid needs a HIP device")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
+        if method is None:
+            method = "improved" if z_offset else "no_offset"
+        Wz = (1 if method == "original" else W) if Wz is None else Wz
+        z0 = x0 if z0 is None else z0
         with torch.cuda.device(self.device):
-            self._p = grid_create(N, L, W, x0, wmax) if z_offset else \
-                grid_create_variant(N, L, W, x0, wmax, False)
+            self._p = grid_create_axes(N, L, W, x0, Wz, z0, wmax, METHODS[method], n_bins)
         self.N, self.L, self.W, self.x0, self.wmax = N, L, W, x0, wmax
+        self.axes = grid_plan_axes(self._p)
         self.max_workspace_bytes = max_workspace_bytes
         self.info = grid_plan_info(self._p)
         self._ws = {}

@@ -69,3 +69,35 @@ def test_probe_and_last_skipped_reject_bad_arguments():
     assert wg.lib().wsg_bandwidth_probe(4096, 4104, 64, None) == wg.WSG_EINVAL     # overlapping (and misaligned)
     assert wg.lib().wsg_bandwidth_probe(4096, 4112, 64, None) == wg.WSG_EINVAL     # overlapping
     assert wg.lib().grid_last_skipped(None) == wg.WSG_EINVAL
+
+
+@pytest.mark.parametrize("args", [(64, 0.3, 7, 0.25, 3, 0.2, 100.0), (256, 0.4, 7, 0.25, 1, 0.05, 300.0),
+                                  (96, 0.4, 5, 1 / 3, 5, 1 / 3, 50.0)])
+@pytest.mark.parametrize("z_offset", [True, False])
+def test_axes_planner_matches_oracle(args, z_offset):
+    N, L, W, x0, Wz, z0, wmax = args
+    method = wg.WSG_IMPROVED if z_offset else wg.WSG_IMPROVED_NO_OFFSET
+    got = wg.wsg_plan_params_axes(N, L, W, x0, Wz, z0, wmax, method)
+    p = make_plan(N, L, W, x0, wmax, z_offset=z_offset, Wz=Wz, z0=z0)
+    assert (got["Nprime"], got["t_lo"], got["t_hi"]) == (p.Nprime, p.t_lo, p.t_hi)
+    assert got["n0"] == p.n0 and got["n_scale"] == p.n_scale
+
+
+@pytest.mark.parametrize("n_bins", [0, 1, 20, 470])
+def test_original_planner_matches_oracle(n_bins):
+    from oracle.wstack_original import make_original_plan
+    got = wg.wsg_plan_params_axes(900, 0.1047, 7, 0.25, 1, 0.25, 2715.0, wg.WSG_ORIGINAL, n_bins)
+    p = make_original_plan(900, 0.1047, 7, 0.25, 2715.0, n_bins or None)
+    assert got["t_lo"] == 0 and got["t_hi"] == p.n_bins - 1 and got["n0"] == 1.0
+    assert abs(got["n_scale"] - 1.0 / p.dw) <= 1e-15 * got["n_scale"]
+    if n_bins == 0:
+        assert p.n_bins == 47          # Table 2 row a, eq. N_w
+
+
+def test_axes_planner_rejects_bad_arguments():
+    with pytest.raises(RuntimeError):
+        wg.wsg_plan_params_axes(64, 0.3, 7, 0.25, 3, 0.2, 100.0, wg.WSG_ORIGINAL)   # original needs W_z = 1
+    with pytest.raises(RuntimeError):
+        wg.wsg_plan_params_axes(64, 0.3, 7, 0.25, 8, 0.2, 100.0, wg.WSG_IMPROVED)   # W_z > W
+    with pytest.raises(RuntimeError):
+        wg.wsg_plan_params_axes(64, 0.3, 7, 0.25, 1, 0.2, 0.0, wg.WSG_ORIGINAL)     # no w range to bin

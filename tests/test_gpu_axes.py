@@ -1,0 +1,115 @@
+"""GPU parity for plans with a w-axis gridding function of its own, the
+original W-stacking, and FFT lengths 3 2^a (radix-3 passes), through the C-ABI.
+
+* Improved method with (W_z, z0) != (W, x0) (Sec. 5.2: separate C_z in eqs.
+  gridded-dirty-map and gridded_vis; Sec. 6.1 trades W_z against z0) against
+  the oracle's Algorithms 5/6 with a w-axis design of its own.
+* Original W-stacking (Algorithms 3 and 4: nearest-midpoint w bins, 2-D
+  gridding per bin, bin-midpoint phase, 2-D correction) against the oracle's
+  literal implementation (oracle/wstack_original.py), which shares no code
+  with the library's route (the improved machinery with a W_z = 1 top hat).
+* x0 = 1/3 (N' = 3N/2: 96, 192, 384, 768, 1536, 3072) against the oracle.
+Bars: FP64 1e-10, FP32 1e-6 relative RMS, max-abs within 10x.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import wstack, wstack_original as wo
+from oracle.kernel_design import least_misfit
+from oracle.plan import make_plan
+from paper_2101_11172_amd import inputs
+from paper_2101_11172_amd import wsgrid as wg
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+def rel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def maxrel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def run(plan, uvw, vis, img, prec):
+    cdt, rdt = (torch.complex128, torch.float64) if prec == 64 else (torch.complex64, torch.float32)
+    t_uvw = torch.from_numpy(np.ascontiguousarray(uvw)).to(DEV)
+    g = plan.grid(t_uvw, torch.from_numpy(vis).to(DEV, cdt)).cpu().double().numpy()
+    d = plan.degrid(t_uvw, torch.from_numpy(img).to(DEV, rdt)).cpu().to(torch.complex128).numpy()
+    return g, d
+
+
+def check(name, plan, uvw, vis, img, ref_g, ref_d, tol64=1e-10):
+    for prec, tol in ((64, tol64), (32, 1e-6)):
+        g, d = run(plan, uvw, vis, img, prec)
+        eg, ed = rel(g, ref_g), rel(d, ref_d)
+        print(f"{name} fp{prec}: grid {eg:.3e} degrid {ed:.3e}")
+        assert eg <= tol and ed <= tol, (name, prec, eg, ed)
+        assert maxrel(g, ref_g) <= 10 * tol and maxrel(d, ref_d) <= 10 * tol, (name, prec)
+
+
+@pytest.mark.parametrize("case", [(64, 0.3, 7, 0.25, 3, 0.2, 100.0, True), (64, 0.3, 7, 0.25, 1, 0.05, 60.0, True),
+                                  (128, 0.4, 7, 0.25, 5, 0.25, 150.0, False), (64, 0.3, 4, 0.25, 1, 0.1, 50.0, True),
+                                  (64, 0.3, 7, 0.25, 7, 0.35, 100.0, True)],
+                         ids=["W7Wz3", "W7Wz1", "W7Wz5-nooff", "W4Wz1", "W7Wz7z0.35"])
+def test_own_w_axis_against_oracle(case):
+    N, L, W, x0, Wz, z0, wmax, z_offset = case
+    M = 1500
+    uvw = inputs.uniform_uvw(M, 0.9 * N / (2 * L), wmax, 91)
+    vis, img = inputs.random_vis(M, 92), inputs.random_image(N, 93)
+    op = make_plan(N, L, W, x0, wmax, z_offset=z_offset, Wz=Wz, z0=z0)
+    lm, lmz = least_misfit(W, x0), least_misfit(Wz, z0)
+    ref_g = wstack.grid(op, lm, uvw, vis, lmz=lmz)
+    ref_d = wstack.degrid(op, lm, uvw, img, lmz=lmz)
+    plan = wg.Plan(N, L, W, x0, wmax, device=DEV, Wz=Wz, z0=z0, method="improved" if z_offset else "no_offset")
+    assert plan.info["n_layers"] == op.n_layers and plan.info["n_scale"] == op.n_scale
+    assert plan.axes["Wz"] == Wz and plan.axes["z0"] == z0
+    check(f"W{W} Wz{Wz} z0={z0}", plan, uvw, vis, img, ref_g, ref_d)
+    plan.close()
+
+
+@pytest.mark.parametrize("n_bins", [1, 7, 40])
+def test_original_w_stacking_against_oracle(n_bins):
+    N, L, W, x0, wmax, M = 64, 0.5, 7, 0.25, 400.0, 2000
+    uvw = inputs.uniform_uvw(M, 0.9 * N / (2 * L), wmax, 101)
+    uvw[7, 2] = wmax                              # w = wmax: the last bin is closed
+    uvw[8, 2] = -wmax
+    vis, img = inputs.random_vis(M, 102), inputs.random_image(N, 103)
+    op, lm = wo.make_original_plan(N, L, W, x0, wmax, n_bins), least_misfit(W, x0)
+    ref_g, ref_d = wo.grid(op, lm, uvw, vis), wo.degrid(op, lm, uvw, img)
+    plan = wg.Plan(N, L, W, x0, wmax, device=DEV, method="original", n_bins=n_bins)
+    assert plan.info["n_layers"] == n_bins and plan.axes["n_bins"] == n_bins and plan.axes["Wz"] == 1
+    check(f"original N_w={n_bins}", plan, uvw, vis, img, ref_g, ref_d)
+    plan.close()
+
+
+def test_original_default_bins_is_eq_N_w():
+    N, L, W, x0, wmax = 64, 0.5, 7, 0.25, 400.0
+    plan = wg.Plan(N, L, W, x0, wmax, device=DEV, method="original")
+    assert plan.info["n_layers"] == wo.make_original_plan(N, L, W, x0, wmax).n_bins == 163
+    plan.close()
+
+
+@pytest.mark.parametrize("N,W,wmax,M", [(64, 7, 100.0, 1200), (128, 5, 150.0, 2000), (256, 7, 200.0, 3000),
+                                        (512, 4, 300.0, 4000), (1024, 7, 150.0, 6000), (2048, 4, 20.0, 6000)],
+                         ids=["Np96", "Np192", "Np384", "Np768", "Np1536", "Np3072"])
+def test_radix3_fft_lengths_against_oracle(N, W, wmax, M):
+    L, x0 = 0.4, 1 / 3
+    op, lm = make_plan(N, L, W, x0, wmax), least_misfit(W, x0)
+    assert op.Nprime == 3 * N // 2
+    uvw = inputs.uniform_uvw(M, 0.9 * N / (2 * L), wmax, 111)
+    vis, img = inputs.random_vis(M, 112), inputs.random_image(N, 113)
+    ref_g, ref_d = wstack.grid(op, lm, uvw, vis), wstack.degrid(op, lm, uvw, img)
+    plan = wg.Plan(N, L, W, x0, wmax, device=DEV)
+    assert plan.info["Nprime"] == op.Nprime
+    check(f"x0=1/3 N'={op.Nprime}", plan, uvw, vis, img, ref_g, ref_d)
+    plan.close()
+
+
+def test_uncompiled_width_pair_is_rejected():
+    with pytest.raises(RuntimeError, match="not compiled"):
+        wg.Plan(64, 0.3, 9, 0.25, 100.0, device=DEV, Wz=2, z0=0.1)
