@@ -104,8 +104,11 @@ def source_digest() -> str:
     import re
 
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "fft.hpp", "common.hpp", "wsgrid.hip"):
-        text = open(os.path.join(ROOT, "paper_2101_11172_amd", "csrc", f)).read()
+    csrc = os.path.join(ROOT, "paper_2101_11172_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if not f.endswith((".hpp", ".hip", ".inl")):
+            continue
+        text = open(os.path.join(csrc, f)).read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())
@@ -317,6 +320,87 @@ def timed(step, steps: int):
     return (t1 - t0) * 1e3 / steps, wsgrid.wsg_stage_times()
 
 
+def channels_multi_main(args) -> int:
+    """One grid_visibilities_multi plus one degrid_visibilities_multi of 32
+    channels (1.0-1.8 GHz on the wide-field array, 4-10M visibilities each
+    after random flagging, 224M in all) with image sizes per channel: the
+    smallest of 1024^2, 1536^2, 2048^2 that Nyquist-samples the channel (1536^2
+    up to 1.35 GHz, N' = 3072; 2048^2 above, N' = 4096), each size group on one
+    plan with the group's largest |w|; FP32."""
+    import numpy as np
+    import torch
+
+    from paper_2101_11172_amd import inputs, wsgrid
+
+    dev = torch.device("cuda", 0)
+    log("generating the batched-channel workload")
+    w = inputs.channels_workload()
+    L, W, x0, counts, freqs = w["L"], w["W"], w["x0"], w["counts"], w["freqs"]
+    sizes = inputs.channel_image_sizes(freqs)
+    M, C = int(sum(counts)), len(counts)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    group_wmax = {}
+    for c, n in enumerate(sizes):
+        wc = float(np.max(np.abs(w["uvw"][off[c]:off[c + 1], 2]))) if counts[c] else 0.0
+        group_wmax[n] = max(group_wmax.get(n, 0.0), wc)
+    plans = {n: wsgrid.Plan(n, L, W, x0, group_wmax[n], device=dev) for n in sorted(group_wmax)}
+    cap = int(args.max_workspace_gb * (1 << 30))
+    ps = wsgrid.PlanSet([plans[n] for n in sizes], max_workspace_bytes=cap)
+    uvw = torch.from_numpy(w["uvw"]).to(dev)
+    vis = torch.from_numpy(w["vis"]).to(dev)
+    del w
+    img = torch.cat([torch.from_numpy(inputs.random_image(n, 200 + c).astype(np.float32)).reshape(-1)
+                     for c, n in enumerate(sizes)]).to(dev)
+    out_img = torch.empty(ps.map_elements(), dtype=torch.float32, device=dev)
+    out_vis = torch.empty(M, dtype=torch.complex64, device=dev)
+    groups = {n: {"channels": sizes.count(n), "N'": plans[n].info["Nprime"], "w_layers": plans[n].info["n_layers"],
+                  "wmax": group_wmax[n]} for n in plans}
+    log(f"channels={C} M={M} groups={groups}")
+    tuned = None
+    if args.autotune:
+        from paper_2101_11172_amd.autotune import tune_multi
+        tuned = tune_multi(ps, uvw, counts, vis, img, cap)
+        ps.max_workspace_bytes = tuned["workspace_bytes"]
+        log(f"autotune: workspace {tuned['workspace_bytes']} bytes, ms by workspace {tuned['ms']}")
+
+    def step():
+        ps.grid(uvw, counts, vis, out=out_img)
+        ps.degrid(uvw, counts, img, out=out_vis)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    ms, stages = timed(step, args.steps)
+    log(f"channels (per-channel sizes): {ms:.3f} ms/step, {M / (ms * 1e-3):.4e} vis/s")
+    result = {
+        "metric": "batched channels: visibilities/s grid+degrid, 32 channels, image size per channel",
+        "value": M / (ms * 1e-3),
+        "unit": "visibilities/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"batched channels: {C} channels 1.0-1.8 GHz of the wide-field array, 0-60% random "
+                                f"flagging per channel, {M} visibilities, image size per channel "
+                                f"({sizes.count(1536)} x 1536^2, {sizes.count(2048)} x 2048^2), L={L}, W={W}, "
+                                f"x0={x0}, one plan per size group"),
+                   "channels": C, "visibilities": M, "groups": {str(k): v for k, v in groups.items()},
+                   "workspace_bytes": ps.workspace(wsgrid.WSG_F32, counts).numel()},
+        "autotune": tuned,
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+    }
+    print(json.dumps(result), flush=True)
+    for p in plans.values():
+        p.close()
+    return 0
+
+
 def channels_main(args) -> int:
     """One grid_visibilities_batch plus one degrid_visibilities_batch of 32
     channels (1.0-1.8 GHz on the wide-field array, 4-10M visibilities each
@@ -488,6 +572,8 @@ def main() -> int:
                          "channels: one batched grid + degrid of 32 channels per step")
     ap.add_argument("--max-workspace-gb", type=float, default=96.0,
                     help="imaging and channels: workspace cap (layer passes)")
+    ap.add_argument("--one-plan", action="store_true",
+                    help="channels: one 2048^2 plan for every channel (instead of an image size per channel)")
     ap.add_argument("--autotune", action="store_true",
                     help="channels: choose the layers per pass within the cap by timing (autotune.py) first")
     args = ap.parse_args()
@@ -498,7 +584,7 @@ def main() -> int:
     if args.workload == "imaging":
         return imaging_main(args)
     if args.workload == "channels":
-        return channels_main(args)
+        return channels_main(args) if args.one_plan else channels_multi_main(args)
 
     import numpy as np
     import torch

@@ -240,6 +240,36 @@ int degrid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, cons
                               const void* image, void* vis, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Batched channels with plans of their own (image size N_c, wmax, widths):
+ * channel c uses plans[c]; channels that share a plan must be consecutive and
+ * each such run is one grid_visibilities_batch / degrid_visibilities_batch
+ * (one launch per stage over the run's channels), the runs one after the
+ * other on `stream` with the same workspace.  All plans on one device.
+ *   M      [nch] visibility counts (host); uvw, vis: the channels' visibilities
+ *          one after the other, as for the _batch calls;
+ *   dirty / image: the channels' N_c x N_c maps one after the other (channel
+ *          c at offset sum_{c' < c} N_c'^2 elements);
+ *   ws     ws_bytes >= grid_workspace_bytes_multi(nch, plans, prec, M, 1).
+ * Channel c's result equals the single-channel call with plans[c] (degrid:
+ * bit for bit).  Errors as for the _batch calls, plus WSG_EINVAL when a plan
+ * pointer is null or a plan recurs after another plan's run.
+ */
+int grid_visibilities_multi(int nch, const wsg_plan* const* plans, wsg_prec prec, const int64_t* M,
+                            const double* uvw, const void* vis, void* dirty, void* ws, size_t ws_bytes,
+                            void* stream);
+int degrid_visibilities_multi(int nch, const wsg_plan* const* plans, wsg_prec prec, const int64_t* M,
+                              const double* uvw, const void* image, void* vis, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/*
+ * Workspace (bytes) of the _multi calls: the largest over the runs of
+ * grid_workspace_bytes_batch(run plan, prec, run channels, run visibilities,
+ * min_passes).  0 on a bad argument.
+ */
+size_t grid_workspace_bytes_multi(int nch, const wsg_plan* const* plans, wsg_prec prec, const int64_t* M,
+                                  int min_passes);
+
+/*
  * Workspace (bytes) of a batched call with nch channels and M visibilities in
  * all: min_passes = 0 holds every layer of every channel at once, 1 gives the
  * smallest workspace the call accepts (one tile layer of 16 w-layers per

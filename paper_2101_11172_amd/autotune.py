@@ -67,3 +67,50 @@ def tune_pass_layers(plan: "wg.Plan", uvw: torch.Tensor, counts, vis: torch.Tens
         torch.cuda.empty_cache()      # the next candidate may need the memory back
     best = min(timings, key=timings.get)
     return {"workspace_bytes": by_layers[best], "pass_layers": best, "ms": timings}
+
+
+def tune_multi(planset: "wg.PlanSet", uvw: torch.Tensor, counts, vis: torch.Tensor, image: torch.Tensor,
+               max_workspace_bytes: int, n_candidates: int = 4, repeats: int = 2) -> dict:
+    """As tune_pass_layers for channels with plans of their own (a PlanSet):
+    times one grid_visibilities_multi plus one degrid_visibilities_multi for a
+    few workspace sizes between the smallest the calls accept and the cap (the
+    workspace sets every run's layers per pass) and returns the fastest.
+    image: the packed maps of the matching real precision."""
+    counts = [int(c) for c in counts]
+    planset._check(uvw, counts)
+    prec = wg.WSG_F32 if vis.dtype == torch.complex64 else wg.WSG_F64
+    rdt = torch.float32 if prec == wg.WSG_F32 else torch.float64
+    if vis.dtype not in (torch.complex64, torch.complex128) or image.dtype != rdt \
+            or image.shape != (planset.map_elements(),) or vis.shape != (uvw.shape[0],):
+        raise ValueError("vis [M] complex and packed image maps of the matching real precision are required")
+    ptrs = planset._ptrs()
+    least = wg.grid_workspace_bytes_multi(ptrs, prec, counts, True)
+    top = min(wg.grid_workspace_bytes_multi(ptrs, prec, counts), int(max_workspace_bytes))
+    if top < least:
+        raise ValueError(f"the cap is below the smallest workspace ({least} bytes)")
+    sizes = sorted({least + (top - least) * i // max(1, n_candidates - 1) for i in range(n_candidates)})
+    stream = torch.cuda.current_stream(planset.device)
+    dirty = torch.empty(planset.map_elements(), dtype=rdt, device=planset.device)
+    out = torch.empty(uvw.shape[0], dtype=vis.dtype, device=planset.device)
+    timings = {}
+    for nbytes in sizes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=planset.device)
+
+        def step():
+            wg.grid_visibilities_multi(ptrs, prec, counts, uvw.data_ptr(), vis.data_ptr(), dirty.data_ptr(),
+                                       ws.data_ptr(), nbytes, stream.cuda_stream)
+            wg.degrid_visibilities_multi(ptrs, prec, counts, uvw.data_ptr(), image.data_ptr(), out.data_ptr(),
+                                         ws.data_ptr(), nbytes, stream.cuda_stream)
+
+        step()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(repeats):
+            step()
+        end.record(stream)
+        end.synchronize()
+        timings[nbytes] = start.elapsed_time(end) / repeats
+        del ws
+        torch.cuda.empty_cache()
+    best = min(timings, key=timings.get)
+    return {"workspace_bytes": best, "ms": timings}

@@ -698,6 +698,93 @@ int degrid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, cons
                            : run<double>(plan, false, M, tot, uvw, image, vis, ws, L, s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Runs of consecutive channels with one plan: [first channel, end channel).
+int plan_runs(int nch, const wsg_plan* const* plans, std::vector<std::pair<int, int>>* runs) {
+    if (nch < 1 || nch > kMaxChannels) return fail(WSG_EINVAL, "channels must be in [1, 64]");
+    if (!plans) return fail(WSG_EINVAL, "null plan list");
+    runs->clear();
+    for (int c = 0; c < nch; ++c) {
+        if (!plans[c]) return fail(WSG_EINVAL, "null plan for a channel");
+        if (c > 0 && plans[c] == plans[c - 1]) {
+            runs->back().second = c + 1;
+            continue;
+        }
+        for (const auto& r : *runs)
+            if (plans[r.first] == plans[c]) return fail(WSG_EINVAL, "channels sharing a plan must be consecutive");
+        runs->push_back({c, c + 1});
+    }
+    return WSG_OK;
+}
+
+// One batched call per run; `a` advances over the inputs, `b` over the outputs
+// (visibility-sized or map-sized by direction).
+int run_multi(bool grid, int nch, const wsg_plan* const* plans, wsg_prec prec, const int64_t* M, const double* uvw,
+              const void* in, void* out, void* ws, size_t ws_bytes, void* stream) {
+    std::vector<std::pair<int, int>> runs;
+    int rc = plan_runs(nch, plans, &runs);
+    if (rc != WSG_OK) return rc;
+    if (!M) return fail(WSG_EINVAL, "null visibility counts");
+    const size_t cs = prec == WSG_F64 ? 16 : 8, rs = prec == WSG_F64 ? 8 : 4;
+    int64_t voff = 0;
+    size_t moff = 0;
+    for (const auto& r : runs) {
+        const wsg_plan* p = plans[r.first];
+        const int n = r.second - r.first;
+        int64_t mrun = 0;
+        for (int c = r.first; c < r.second; ++c) mrun += M[c] < 0 ? 0 : M[c];
+        const size_t map = size_t(p->pp.N) * size_t(p->pp.N) * size_t(n);
+        const double* u = uvw ? uvw + 3 * voff : nullptr;
+        if (grid) {
+            const void* v = in ? static_cast<const char*>(in) + size_t(voff) * cs : nullptr;
+            void* d = out ? static_cast<char*>(out) + moff * rs : nullptr;
+            rc = grid_visibilities_batch(p, prec, n, M + r.first, u, v, d, ws, ws_bytes, stream);
+        } else {
+            const void* im = in ? static_cast<const char*>(in) + moff * rs : nullptr;
+            void* v = out ? static_cast<char*>(out) + size_t(voff) * cs : nullptr;
+            rc = degrid_visibilities_batch(p, prec, n, M + r.first, u, im, v, ws, ws_bytes, stream);
+        }
+        if (rc != WSG_OK) return rc;
+        voff += mrun;
+        moff += map;
+    }
+    return WSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grid_visibilities_multi(int nch, const wsg_plan* const* plans, wsg_prec prec, const int64_t* M,
+                            const double* uvw, const void* vis, void* dirty, void* ws, size_t ws_bytes,
+                            void* stream) {
+    return run_multi(true, nch, plans, prec, M, uvw, vis, dirty, ws, ws_bytes, stream);
+}
+
+int degrid_visibilities_multi(int nch, const wsg_plan* const* plans, wsg_prec prec, const int64_t* M,
+                              const double* uvw, const void* image, void* vis, void* ws, size_t ws_bytes,
+                              void* stream) {
+    return run_multi(false, nch, plans, prec, M, uvw, image, vis, ws, ws_bytes, stream);
+}
+
+size_t grid_workspace_bytes_multi(int nch, const wsg_plan* const* plans, wsg_prec prec, const int64_t* M,
+                                  int min_passes) {
+    std::vector<std::pair<int, int>> runs;
+    if (plan_runs(nch, plans, &runs) != WSG_OK || !M) return 0;
+    size_t best = 0;
+    for (const auto& r : runs) {
+        int64_t mrun = 0;
+        for (int c = r.first; c < r.second; ++c) mrun += M[c];
+        const size_t b = grid_workspace_bytes_batch(plans[r.first], prec, r.second - r.first, mrun, min_passes);
+        if (b == 0) return 0;
+        best = std::max(best, b);
+    }
+    return best;
+}
+
 int grid_visibilities(const wsg_plan* plan, wsg_prec prec, int64_t M, const double* uvw, const void* vis, void* dirty,
                       void* ws, size_t ws_bytes, void* stream) {
     return grid_visibilities_batch(plan, prec, 1, &M, uvw, vis, dirty, ws, ws_bytes, stream);

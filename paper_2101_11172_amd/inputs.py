@@ -151,6 +151,14 @@ def channels_workload(n_channels: int = 32, n_dumps: int = 4960, seed: int = 3, 
                 vis=random_vis(uvw.shape[0], seed + 100, vis_dtype))
 
 
+def channel_image_sizes(freqs, n_top: int = 2048, sizes=(1024, 1536, 2048)) -> list:
+    """Image size per channel for the batched-channel workload: the smallest
+    2^a or 3 2^a size in [1024, 2048] that Nyquist-samples the channel's uv
+    extent, which scales with frequency (the top channel needs n_top)."""
+    top = max(freqs)
+    return [next(n for n in sizes if n >= n_top * f / top - 1e-9) for f in freqs]
+
+
 def workload(name: str, seed: int | None = None, n_dumps: int = 4960,
              vis_dtype=np.complex64) -> dict:
     """Parameters and inputs of a named workload (see module docstring)."""

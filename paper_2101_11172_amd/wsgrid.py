@@ -58,6 +58,14 @@ _SIGNATURES = {
                                                  ctypes.c_size_t, ctypes.c_void_p]),
     "grid_workspace_bytes_batch": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                                      ctypes.c_int]),
+    "grid_visibilities_multi": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, _c_int64_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_size_t, ctypes.c_void_p]),
+    "degrid_visibilities_multi": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, _c_int64_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_size_t, ctypes.c_void_p]),
+    "grid_workspace_bytes_multi": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, _c_int64_p,
+                                                     ctypes.c_int]),
     "grid_layers_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                             ctypes.c_size_t]),
     "grid_skipped": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -216,6 +224,29 @@ def degrid_visibilities_batch(plan: int, prec: int, M, uvw_ptr: int, image_ptr: 
                               ws_ptr: int, ws_bytes: int, stream: int) -> None:
     _err(lib().degrid_visibilities_batch(plan, prec, len(M), _counts(M), uvw_ptr, image_ptr, vis_ptr, ws_ptr,
                                          ws_bytes, stream), "degrid_visibilities_batch")
+
+
+def _plan_array(plans) -> ctypes.Array:
+    return (ctypes.c_void_p * len(plans))(*[int(p) for p in plans])
+
+
+def grid_visibilities_multi(plans, prec: int, M, uvw_ptr: int, vis_ptr: int, dirty_ptr: int, ws_ptr: int,
+                            ws_bytes: int, stream: int) -> None:
+    _err(lib().grid_visibilities_multi(len(M), _plan_array(plans), prec, _counts(M), uvw_ptr, vis_ptr, dirty_ptr,
+                                       ws_ptr, ws_bytes, stream), "grid_visibilities_multi")
+
+
+def degrid_visibilities_multi(plans, prec: int, M, uvw_ptr: int, image_ptr: int, vis_ptr: int, ws_ptr: int,
+                              ws_bytes: int, stream: int) -> None:
+    _err(lib().degrid_visibilities_multi(len(M), _plan_array(plans), prec, _counts(M), uvw_ptr, image_ptr, vis_ptr,
+                                         ws_ptr, ws_bytes, stream), "degrid_visibilities_multi")
+
+
+def grid_workspace_bytes_multi(plans, prec: int, M, min_passes: bool = False) -> int:
+    n = lib().grid_workspace_bytes_multi(len(M), _plan_array(plans), prec, _counts(M), 1 if min_passes else 0)
+    if n == 0:
+        raise RuntimeError(f"grid_workspace_bytes_multi: bad argument ({grid_last_error()})")
+    return n
 
 
 def grid_skipped(plan: int, ws_ptr: int, stream: int) -> int:
@@ -427,6 +458,89 @@ class Plan:
     def skipped(self, prec: int) -> int:
         ws = self._ws[prec]
         return grid_skipped(self._p, ws.data_ptr(), torch.cuda.current_stream(self.device).cuda_stream)
+
+
+class PlanSet:
+    """Channels with plans of their own (grid/degrid_visibilities_multi).
+
+    plans[c] is channel c's Plan (image size, wmax and widths per plan);
+    channels that share a plan must be consecutive.  Maps are packed channel
+    after channel (N_c^2 elements each); maps() gives the [N_c, N_c] views.
+    max_workspace_bytes caps the workspace (layer passes below the full size).
+    """
+
+    def __init__(self, plans, max_workspace_bytes: int | None = None):
+        self.plans = list(plans)
+        self.device = self.plans[0].device
+        if any(p.device != self.device for p in self.plans):
+            raise ValueError("all plans must be on one device")
+        self.max_workspace_bytes = max_workspace_bytes
+        self._ws = {}
+
+    def _ptrs(self):
+        return [p._p for p in self.plans]
+
+    def map_elements(self) -> int:
+        return sum(p.N * p.N for p in self.plans)
+
+    def maps(self, packed: torch.Tensor):
+        out, off = [], 0
+        for p in self.plans:
+            out.append(packed[off:off + p.N * p.N].view(p.N, p.N))
+            off += p.N * p.N
+        return out
+
+    def workspace(self, prec: int, counts) -> torch.Tensor:
+        need = grid_workspace_bytes_multi(self._ptrs(), prec, counts)
+        if self.max_workspace_bytes is not None and need > self.max_workspace_bytes:
+            need = max(grid_workspace_bytes_multi(self._ptrs(), prec, counts, True), int(self.max_workspace_bytes))
+        ws = self._ws.get(prec)
+        if ws is None or ws.numel() < need or (self.max_workspace_bytes is not None and ws.numel() > need):
+            self._ws.pop(prec, None)
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws[prec] = ws
+        return ws
+
+    def _check(self, uvw, counts):
+        counts = [int(c) for c in counts]
+        if len(counts) != len(self.plans):
+            raise ValueError("one count per channel (plan)")
+        M = self.plans[0]._check_uvw(uvw)
+        if min(counts) < 0 or sum(counts) != M:
+            raise ValueError("counts must be non-negative and add up to the number of visibilities")
+        return M, counts
+
+    def grid(self, uvw: torch.Tensor, counts, vis: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        M, counts = self._check(uvw, counts)
+        if vis.dtype not in (torch.complex64, torch.complex128) or vis.shape != (M,) or not vis.is_contiguous() \
+                or vis.device != self.device:
+            raise ValueError("vis must be a contiguous complex64/complex128 [M] tensor on the plans' device")
+        prec = _PREC[vis.dtype]
+        rdt = torch.float32 if prec == WSG_F32 else torch.float64
+        if out is None:
+            out = torch.empty(self.map_elements(), dtype=rdt, device=self.device)
+        elif out.dtype != rdt or out.shape != (self.map_elements(),) or not out.is_contiguous():
+            raise ValueError("out must be the packed maps")
+        ws = self.workspace(prec, counts)
+        grid_visibilities_multi(self._ptrs(), prec, counts, uvw.data_ptr(), vis.data_ptr(), out.data_ptr(),
+                                ws.data_ptr(), ws.numel(), torch.cuda.current_stream(self.device).cuda_stream)
+        return out
+
+    def degrid(self, uvw: torch.Tensor, counts, image: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        M, counts = self._check(uvw, counts)
+        if image.dtype not in (torch.float32, torch.float64) or image.shape != (self.map_elements(),) \
+                or not image.is_contiguous() or image.device != self.device:
+            raise ValueError("image must be the packed float32/float64 maps on the plans' device")
+        prec = _PREC[image.dtype]
+        cdt = torch.complex64 if prec == WSG_F32 else torch.complex128
+        if out is None:
+            out = torch.empty(M, dtype=cdt, device=self.device)
+        elif out.dtype != cdt or out.shape != (M,) or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or shape")
+        ws = self.workspace(prec, counts)
+        degrid_visibilities_multi(self._ptrs(), prec, counts, uvw.data_ptr(), image.data_ptr(), out.data_ptr(),
+                                  ws.data_ptr(), ws.numel(), torch.cuda.current_stream(self.device).cuda_stream)
+        return out
 
 
 class DegridFn(torch.autograd.Function):

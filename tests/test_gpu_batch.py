@@ -140,3 +140,47 @@ def test_autotuner_picks_a_working_pass_size():
     assert torch.equal(tuned.degrid_batch(uvw, counts, img), ref)
     tuned.close()
     plan.close()
+
+
+def test_multi_plan_channels_match_single_and_oracle():
+    """grid/degrid_visibilities_multi: channels with plans of their own (image
+    sizes 64^2 and 96^2, N' = 128 and 192, and their own wmax), consecutive
+    channels sharing a plan batched together; each channel against the
+    single-channel call with its plan (degrid bit for bit) and the oracle."""
+    L, W, x0 = 0.3, 7, 0.25
+    spec = [(64, 80.0), (64, 80.0), (96, 120.0), (96, 120.0), (96, 120.0)]     # (N_c, wmax of its plan)
+    counts = [600, 0, 900, 400, 1100]
+    plans = {key: wg.Plan(key[0], L, W, x0, key[1], device=DEV) for key in sorted(set(spec))}
+    ps = wg.PlanSet([plans[k] for k in spec])
+    uvws = [inputs.uniform_uvw(m, 0.9 * n / (2 * L), wmax, 300 + c) for c, ((n, wmax), m) in enumerate(zip(spec, counts))]
+    vis = [inputs.random_vis(m, 310 + c) for c, m in enumerate(counts)]
+    imgs = [inputs.random_image(n, 320 + c) for c, (n, _) in enumerate(spec)]
+    uvw_all = torch.from_numpy(np.concatenate(uvws)).to(DEV)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    for prec, tol in ((64, 1e-10), (32, 1e-6)):
+        cdt, rdt = (torch.complex128, torch.float64) if prec == 64 else (torch.complex64, torch.float32)
+        v_all = torch.from_numpy(np.concatenate(vis)).to(DEV, cdt)
+        img_all = torch.cat([torch.from_numpy(f).to(DEV, rdt).reshape(-1) for f in imgs])
+        maps = ps.maps(ps.grid(uvw_all, counts, v_all))
+        vout = ps.degrid(uvw_all, counts, img_all).cpu().to(torch.complex128).numpy()
+        for c, (n, wmax) in enumerate(spec):
+            p = plans[(n, wmax)]
+            op, lm = make_plan(n, L, W, x0, wmax), least_misfit(W, x0)
+            u = torch.from_numpy(uvws[c]).to(DEV)
+            g1 = p.grid(u, torch.from_numpy(vis[c]).to(DEV, cdt)).cpu().double().numpy()
+            gm = maps[c].cpu().double().numpy()
+            d1 = p.degrid(u, torch.from_numpy(imgs[c]).to(DEV, rdt)).cpu().to(torch.complex128).numpy()
+            dm = vout[off[c]:off[c + 1]]
+            assert np.array_equal(dm, d1), (prec, c)
+            if counts[c] == 0:
+                assert not np.any(gm)
+                continue
+            assert rel(gm, g1) <= (1e-14 if prec == 64 else 1e-6), (prec, c)
+            assert rel(gm, wstack.grid(op, lm, uvws[c], vis[c])) <= tol, (prec, c)
+            assert rel(dm, wstack.degrid(op, lm, uvws[c], imgs[c])) <= tol, (prec, c)
+    # a plan that recurs after another plan's run is rejected before any launch
+    bad = wg.PlanSet([plans[(64, 80.0)], plans[(96, 120.0)], plans[(64, 80.0)]])
+    with pytest.raises(RuntimeError, match="consecutive"):
+        bad.grid(uvw_all[:30].contiguous(), [10, 10, 10], torch.zeros(30, dtype=torch.complex64, device=DEV))
+    for p in plans.values():
+        p.close()
