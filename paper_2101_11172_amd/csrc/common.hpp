@@ -10,6 +10,17 @@ struct cpx {
     R x, y;
 };
 
+// Store of a complex value that is read back only by a later kernel (the FFT
+// intermediates): non-temporal, so it streams through the caches.
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_stream(cpx<float>* p, cpx<float> v) {
+    __builtin_nontemporal_store(nt_f2{v.x, v.y}, reinterpret_cast<nt_f2*>(p));
+}
+__device__ __forceinline__ void store_stream(cpx<double>* p, cpx<double> v) {
+    __builtin_nontemporal_store(nt_d2{v.x, v.y}, reinterpret_cast<nt_d2*>(p));
+}
+
 template <typename R>
 __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};

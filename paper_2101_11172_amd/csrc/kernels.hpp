@@ -18,23 +18,26 @@ __global__ void k_fill(T* __restrict__ p, size_t n, T v) {
 
 // Streaming copy for the bandwidth probe: each block walks kProbeUnroll
 // consecutive 16-byte vectors per thread per round (all loads issued before
-// the stores), rounds strided by the whole grid.
+// the stores, non-temporal both ways), rounds strided by the whole grid.  Of
+// the shapes measured (128-1024 threads, 4-16 vectors, 512-16384 blocks,
+// temporal or not) this one streamed fastest.
 constexpr int kProbeThreads = 256;
-constexpr int kProbeUnroll = 4;
-static __global__ void __launch_bounds__(kProbeThreads) k_copy_probe(const uint4* __restrict__ src, uint4* __restrict__ dst,
-                                                            size_t n) {
+constexpr int kProbeUnroll = 8;
+typedef unsigned int probe_vec __attribute__((ext_vector_type(4)));
+static __global__ void __launch_bounds__(kProbeThreads) k_copy_probe(const probe_vec* __restrict__ src,
+                                                                   probe_vec* __restrict__ dst, size_t n) {
     const size_t step = size_t(gridDim.x) * kProbeThreads * kProbeUnroll;
     for (size_t base = size_t(blockIdx.x) * kProbeThreads * kProbeUnroll + threadIdx.x; base < n; base += step) {
-        uint4 v[kProbeUnroll];
+        probe_vec v[kProbeUnroll];
 #pragma unroll
         for (int u = 0; u < kProbeUnroll; ++u) {
             const size_t i = base + size_t(u) * kProbeThreads;
-            if (i < n) v[u] = src[i];
+            if (i < n) v[u] = __builtin_nontemporal_load(src + i);
         }
 #pragma unroll
         for (int u = 0; u < kProbeUnroll; ++u) {
             const size_t i = base + size_t(u) * kProbeThreads;
-            if (i < n) dst[i] = v[u];
+            if (i < n) __builtin_nontemporal_store(v[u], dst + i);
         }
     }
 }
@@ -611,7 +614,7 @@ template <typename R, int W, int WZ>
 struct ScatterCfg {
     // records per wave round: 16 (four lanes stage each) for W <= 7, where the
     // block then fits in 40 KB of LDS (FP32: four blocks per CU) or 80 KB
-    // (FP64: two), else 32 (two lanes each)
+    // (FP64: two), else 32 (two lanes each; at W = 7 that measured 8 % slower)
     static constexpr int kWaveBatch = W <= 7 ? 16 : 32;
     static constexpr int kLanesPerRecord = 64 / kWaveBatch;
     // waves per block, each on its own part of the tile's record list (eight
@@ -1088,7 +1091,7 @@ __global__ void __launch_bounds__((FftCfg<R, NP>::kNLt * FftCfg<R, NP>::T))
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int q = shift_half<Np>(j + T * k, half);
-            if (q < N) dst[q] = v[k];
+            if (q < N) store_stream(dst + q, v[k]);
         }
     }
 }
@@ -1225,7 +1228,7 @@ __global__ void __launch_bounds__((FftCfg<R, NP>::kNLr * FftCfg<R, NP>::T))
             cpx<R>* dst = inter + ((size_t)(seg0 + t) * N + q) * Np;
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if ((live >> k) & 1u) dst[j + T * k] = v[k];
+                if ((live >> k) & 1u) store_stream(dst + j + T * k, v[k]);
         }
     }
 }
@@ -1320,7 +1323,8 @@ __global__ void __launch_bounds__(THREADS) k_transpose(const cpx<R>* __restrict_
     cpx<R>* dst = out + (size_t)t * A * B;
     for (int i = threadIdx.x; i < 64 * 64; i += THREADS) {
         const int b = b0 + i / 64, a = a0 + i % 64;
-        if (a < A && b < B && live[(R_IN ? i % 64 : i / 64) / kTileR]) dst[(size_t)b * A + a] = tile[i % 64][i / 64];
+        if (a < A && b < B && live[(R_IN ? i % 64 : i / 64) / kTileR])
+            store_stream(dst + (size_t)b * A + a, tile[i % 64][i / 64]);
     }
 }
 

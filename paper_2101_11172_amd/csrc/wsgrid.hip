@@ -834,7 +834,7 @@ int wsg_bandwidth_probe(const void* src, void* dst, size_t bytes, void* stream) 
     const unsigned blocks = unsigned(std::min<size_t>((n + kProbeThreads * kProbeUnroll - 1) /
                                                           (kProbeThreads * kProbeUnroll), 256 * 64));
     hipLaunchKernelGGL(k_copy_probe, dim3(blocks), dim3(kProbeThreads), 0, static_cast<hipStream_t>(stream),
-                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+                       static_cast<const probe_vec*>(src), static_cast<probe_vec*>(dst), n);
     WSG_HIP(hipGetLastError());
     return WSG_OK;
 }
