@@ -566,8 +566,9 @@ def main() -> int:
                     help="first run one device-to-device copy of this many GB (counter calibration)")
     ap.add_argument("--no-z-offset", action="store_true",
                     help="widefield: the planner variant without z offset (Sec. 5.3; about twice the layers)")
-    ap.add_argument("--workload", choices=("widefield", "lowcost", "imaging", "channels"), default="widefield",
-                    help="lowcost: the wide-field geometry at W=4, x0=0.5; "
+    ap.add_argument("--workload", choices=("widefield", "lowcost", "widefield3", "imaging", "channels"),
+                    default="widefield",
+                    help="lowcost: the wide-field geometry at W=4, x0=0.5; widefield3: at x0=1/3 (N'=3072); "
                          "imaging: one differentiable-imaging gradient step per step (4096^2, 50M visibilities); "
                          "channels: one batched grid + degrid of 32 channels per step")
     ap.add_argument("--max-workspace-gb", type=float, default=96.0,
@@ -687,8 +688,9 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (("wide-field single channel" if args.workload == "widefield" else
-                                 "low-cost setting on the wide-field geometry")
+        "config": {"workload": ({"widefield": "wide-field single channel",
+                                  "lowcost": "low-cost setting on the wide-field geometry",
+                                  "widefield3": "wide-field geometry at x0=1/3 (radix-3 transforms)"}[args.workload]
                                 + f": {N}x{N} image, L={L}, W={W}, x0={x0}, {M} "
                                 f"visibilities (64 antennas in a 5 km disc, +-1 h tracks, dec -30, 1.4 GHz, "
                                 f"uvw scaled to a Nyquist-sampled image), {nl} w-layers, N'={Np}"

@@ -18,6 +18,8 @@ Workloads (all seeded with ``numpy.random.default_rng``):
   i.e. the image is Nyquist-sampled; complex N(0, 1) values (complex64 or
   complex128); W = 7, x0 = 0.25.
 * ``lowcost`` -- the ``widefield`` geometry with W = 4, x0 = 0.5.
+* ``widefield3`` -- the ``widefield`` geometry with x0 = 1/3 (N' = 3072, radix-3
+  transforms; Sec. 6.3's cropping discussion).
 * ``table2`` (``table2_workload``) -- stand-in for the Table 2 simulation: a
   512 x 512 image of a 6 degree field, 34 point sources, 27 antennas, 11
   two-minute snapshots from -5 h to +5 h, w scaled to the field's product
@@ -168,12 +170,12 @@ def workload(name: str, seed: int | None = None, n_dumps: int = 4960,
         return dict(name=name, N=256, L=0.2, W=7, x0=0.25, wmax=300.0, uvw=uvw,
                     vis=random_vis(5000, seed + 100, np.complex128),
                     sky=random_sky(256, 20, seed + 200))
-    if name in ("widefield", "lowcost"):
+    if name in ("widefield", "lowcost", "widefield3"):
         seed = 1 if seed is None else seed
         N, L = 2048, 0.4
         uvw = array_uvw(64, 5000.0, -30.0, -30.0, 1.0, n_dumps, 1.4e9, seed)
         uvw = scale_to_image(uvw, N, L)
-        W, x0 = (7, 0.25) if name == "widefield" else (4, 0.5)
+        W, x0 = {"widefield": (7, 0.25), "lowcost": (4, 0.5), "widefield3": (7, 1 / 3)}[name]
         return dict(name=name, N=N, L=L, W=W, x0=x0, wmax=float(np.max(np.abs(uvw[:, 2]))),
                     uvw=uvw, vis=random_vis(uvw.shape[0], seed + 100, vis_dtype),
                     sky=None)
