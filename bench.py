@@ -115,8 +115,14 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, prec: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on the current sources."""
+def workload_key(name: str, N: int, W: int, x0: float, M: int, n_layers: int) -> str:
+    """Names the workload a counter run was taken on (counters hold for that one only)."""
+    return f"{name} N={N} W={W} x0={x0:.6g} M={M} layers={n_layers}"
+
+
+def counters(key: str):
+    """The committed rocprofv3 counter summary, if it was taken on the current
+    sources and on this workload; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -124,23 +130,23 @@ def traffic_for(kernel: str, prec: str):
         t = json.load(open(path))
     except ValueError:
         return None
-    if t.get("source_digest") != source_digest():
+    if t.get("source_digest") != source_digest() or t.get("workload") != key:
         return None
-    return t.get("per_launch_bytes", {}).get(f"{kernel}:{prec}")
+    return t
 
 
-def issue_for(kernel: str, prec: str):
+def traffic_for(kernel: str, prec: str, key: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on the current sources."""
+    t = counters(key)
+    return None if t is None else t.get("per_launch_bytes", {}).get(f"{kernel}:{prec}")
+
+
+def issue_for(kernel: str, prec: str, key: str):
     """VALU wave instructions per launch and their issue time from committed
     rocprofv3 counter runs, if taken on the current sources (a wave64 VALU
     instruction holds a SIMD for 4 cycles: 1024 SIMDs at 2.4 GHz)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    try:
-        t = json.load(open(path))
-    except ValueError:
-        return None
-    if t.get("source_digest") != source_digest():
+    t = counters(key)
+    if t is None:
         return None
     n = t.get("valu_per_launch", {}).get(f"{kernel}:{prec}")
     if n is None:
@@ -665,12 +671,13 @@ def main() -> int:
     dom = max(tab32, key=lambda k: tab32[k]["ms"])
     d = tab32[dom]
     achievable = probe["GBps"] if probe else None
+    key = workload_key(args.workload + ("-no-z-offset" if args.no_z_offset else ""), N, W, x0, M, nl)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic_for(dom, "f32"),
+                "frac": d["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic_for(dom, "f32", key),
                 "achievable": achievable, "frac_of_achievable": d["alg_GBps"] / achievable if achievable else None,
                 "alg_bytes_per_call": d["alg_bytes"], "ms_per_call": d["ms"],
                 "launches_per_call": d["launches_per_call"]}
-    issue = issue_for(dom, "f32")
+    issue = issue_for(dom, "f32", key)
     if issue:
         roofline["issue"] = {**issue, "valu_issue_frac": issue["valu_issue_ms"] / d["ms"]}
     total_alg = sum(stage_bytes(s, M, N, Np, nl, False, ws) for s in tab32)

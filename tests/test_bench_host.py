@@ -3,6 +3,8 @@ that fix the algorithmic bytes, against brute force over every support cell of
 every visibility (a tile is occupied when a support cell of some visibility
 lies in it; a visibility visits each tile its W^3 cells meet; a stack line
 (t, r) is live when its row of tiles holds an occupied tile)."""
+import json
+
 import numpy as np
 import pytest
 
@@ -40,3 +42,22 @@ def test_workload_stats_match_brute_force(N, L, wmax, M):
     assert ws["tiles_occupied"] == tiles
     assert ws["tile_visits"] == visits
     assert ws["nonempty_lines"] == lines
+
+
+def test_counters_hold_for_their_workload_only(tmp_path, monkeypatch):
+    # a counter summary is used only on the sources and the workload it was taken on
+    (tmp_path / "profiles").mkdir()
+    key = bench.workload_key("widefield", 2048, 7, 0.25, 9999360, 49)
+    t = {"source_digest": bench.source_digest(), "workload": key,
+         "per_launch_bytes": {"grid_tiles:f32": 2.0e9}, "valu_per_launch": {"grid_tiles:f32": 1024 * 2.4e6}}
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(t))
+    digest = bench.source_digest()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_digest", lambda: digest)
+    assert bench.traffic_for("grid_tiles", "f32", key) == 2.0e9
+    assert abs(bench.issue_for("grid_tiles", "f32", key)["valu_issue_ms"] - 4.0) < 1e-12
+    other = bench.workload_key("widefield3", 2048, 7, 1 / 3, 9999360, 39)
+    assert bench.traffic_for("grid_tiles", "f32", other) is None and bench.issue_for("grid_tiles", "f32", other) is None
+    t["source_digest"] = "0" * 16
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(t))
+    assert bench.traffic_for("grid_tiles", "f32", key) is None
