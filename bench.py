@@ -91,6 +91,7 @@ def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict) 
         "degrid_transpose": inter_rows + inter_rows,    # lines the transform along q needs, in and out
         "grid_fft_u": inter_rows + 2 * N * N * r,       # live intermediate, correction in, map out
         "degrid_bin": M * (2 * 24 + rec) + sort,
+        "grid_values": M * (rec + b + rec),             # shared binning: degrid record and vis in, grid record out
         "degrid_fft_p": 2 * N * N * r + inter_rows,     # image, correction in, live intermediate out
         "degrid_fft_q": inter_rows + tiles,             # intermediate rows in, occupied tiles out
         # tiles and records in, one part out per visit; then per record its parts in, the visibility out
@@ -627,18 +628,38 @@ def main() -> int:
     out_img32 = torch.empty((N, N), dtype=torch.float32, device=dev)
     out_vis32 = torch.empty(M, dtype=torch.complex64, device=dev)
 
+    def relrms(a, b):
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+    # The step: uvw binned once (grid_prepare), then one gridding and one
+    # degridding of all visibilities on that binning.
     def step32():
-        plan.grid(uvw, vis32, out=out_img32)
-        plan.degrid(uvw, img32, out=out_vis32)
+        plan.prepare(uvw, torch.float32)
+        plan.grid_prepared(vis32, out=out_img32)
+        plan.degrid_prepared(img32, out=out_vis32)
+
+    # The same work as two independent calls, each binning uvw itself.
+    sep_img32, sep_vis32 = torch.empty_like(out_img32), torch.empty_like(out_vis32)
+
+    def step32_separate():
+        plan.grid(uvw, vis32, out=sep_img32)
+        plan.degrid(uvw, img32, out=sep_vis32)
 
     for i in range(args.warmup):
         step32()
+        step32_separate()
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{args.warmup} done")
     ms32, stages32 = timed(step32, args.steps)
-    log(f"fp32: {ms32:.3f} ms/step, {M / (ms32 * 1e-3):.4e} vis/s")
-    skipped = plan.skipped(wsgrid.WSG_F32)
+    log(f"fp32: {ms32:.3f} ms/step, {M / (ms32 * 1e-3):.4e} vis/s (one binning per step)")
     tab32 = stage_table(stages32, False, M, N, Np, nl, ws, args.steps)
+    skipped = plan.skipped(wsgrid.WSG_F32)
+    ms_sep, stages_sep = timed(step32_separate, args.steps)
+    log(f"fp32 separate calls: {ms_sep:.3f} ms/step, {M / (ms_sep * 1e-3):.4e} vis/s")
+    separate = {"value": M / (ms_sep * 1e-3), "ms_per_step": ms_sep,
+                "stages": stage_table(stages_sep, False, M, N, Np, nl, ws, args.steps),
+                "prepared_vs_separate": {"grid_rel_rms": relrms(out_img32.double(), sep_img32.double()),
+                                         "degrid_equal": bool(torch.equal(out_vis32, sep_vis32))}}
 
     fp64, acc = None, None
     if args.fp64_steps > 0:
@@ -647,18 +668,15 @@ def main() -> int:
         out_vis64 = torch.empty(M, dtype=torch.complex128, device=dev)
 
         def step64():
-            plan.grid(uvw, vis64, out=out_img64)
-            plan.degrid(uvw, img64, out=out_vis64)
+            plan.prepare(uvw, torch.float64)
+            plan.grid_prepared(vis64, out=out_img64)
+            plan.degrid_prepared(img64, out=out_vis64)
 
         step64()
         ms64, stages64 = timed(step64, args.fp64_steps)
         log(f"fp64: {ms64:.3f} ms/step, {M / (ms64 * 1e-3):.4e} vis/s")
         fp64 = {"value": M / (ms64 * 1e-3), "ms_per_step": ms64,
                 "stages": stage_table(stages64, True, M, N, Np, nl, ws, args.fp64_steps)}
-
-        def relrms(a, b):
-            return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
-
         acc = {"grid": relrms(out_img32.double(), out_img64),
                "degrid": relrms(out_vis32.to(torch.complex128), out_vis64)}
 
@@ -703,7 +721,9 @@ def main() -> int:
                                 f"uvw scaled to a Nyquist-sampled image), {nl} w-layers, N'={Np}"
                                 + (", planner without z offset" if args.no_z_offset else "")),
                    "N": N, "L": L, "W": W, "x0": x0, "visibilities": M, "w_layers": nl, "fft_size": Np,
-                   "z_offset": not args.no_z_offset},
+                   "z_offset": not args.no_z_offset,
+                   "step": "uvw binned once (grid_prepare), then one grid and one degrid of all visibilities on "
+                           "that binning; separate_calls: the same two calls each binning uvw itself"},
         "roofline": roofline,
         "whole_step_alg_GBps": total_alg / (ms32 * 1e-3) / 1e9,
         "whole_step_frac_of_peak": total_alg / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -713,8 +733,9 @@ def main() -> int:
         "fp64": fp64,
         "fp32_vs_fp64_rel_rms": acc,
         "stages": tab32,
+        "separate_calls": separate,
         # each call separately: the sum of its stage times (HIP events, FP32)
-        "stage_sum_ms_per_call": {c: sum(v["ms"] for k, v in tab32.items() if k.startswith(c + "_"))
+        "stage_sum_ms_per_call": {c: sum(v["ms"] for k, v in separate["stages"].items() if k.startswith(c + "_"))
                                   for c in ("grid", "degrid")},
         "stack_occupancy": ws,
         "skipped": skipped,

@@ -240,6 +240,40 @@ int degrid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, cons
                               const void* image, void* vis, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * One binning shared by several gridding and degridding calls on the same
+ * visibilities.  The fold (Sec. 5.4), the normalised coordinates, the support
+ * boxes, the tile binning and the phase e^{+-i 2 pi w (n0 - 1)} of Algorithm 5
+ * step 2 and Algorithm 6 steps 4-5 depend on uvw alone, so an imaging loop
+ * that grids and degrids the same visibilities many times (Sec. 7: the
+ * gridding/degridding pair inside a reconstruction) bins them once.
+ * grid_prepare bins nch channels' visibilities (as grid_visibilities_batch:
+ * M [nch] host counts, uvw [sum M][3] float64 device) into ws, a device
+ * workspace of ws_bytes >= grid_workspace_bytes_batch(plan, prec, nch, sum M,
+ * 1), and keeps the binning there for this plan.  The prepared calls then take
+ * only the values:
+ *   grid_visibilities_prepared:   vis [sum M] complex (prec) -> dirty [nch][N][N];
+ *   degrid_visibilities_prepared: image [nch][N][N] real (prec) -> vis [sum M],
+ * with the same ws, ws_bytes and prec.  Their results equal those of
+ * grid_visibilities_batch / degrid_visibilities_batch on the prepared uvw
+ * (degrid bit for bit; grid up to the rounding of the phase product, formed in
+ * FP64 from the stored phase).  The binning stays valid until another call is
+ * made on ws: any grid_prepare or plain call of this plan on ws replaces it (the
+ * library notices and the prepared calls then fail with WSG_EINVAL); calls of
+ * other plans on the same memory are the caller's to avoid.  The plan keeps one
+ * binning (the most recent grid_prepare).  grid_last_skipped and grid_skipped
+ * report the visibilities skipped by the binning.  uvw may change after
+ * grid_prepare returns; the binning keeps what it read.
+ * Errors: as for the batched calls; WSG_EINVAL from a prepared call when this
+ * plan holds no binning in ws for ws_bytes and prec.
+ */
+int grid_prepare(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* M, const double* uvw, void* ws,
+                 size_t ws_bytes, void* stream);
+int grid_visibilities_prepared(const wsg_plan* plan, wsg_prec prec, const void* vis, void* dirty, void* ws,
+                               size_t ws_bytes, void* stream);
+int degrid_visibilities_prepared(const wsg_plan* plan, wsg_prec prec, const void* image, void* vis, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/*
  * Batched channels with plans of their own (image size N_c, wmax, widths):
  * channel c uses plans[c]; channels that share a plan must be consecutive and
  * each such run is one grid_visibilities_batch / degrid_visibilities_batch
@@ -311,12 +345,14 @@ int64_t grid_last_skipped(const wsg_plan* plan);
  *   2 grid FFT pass along v (+ crop)             6 degrid FFT pass along q
  *   3 grid FFT pass along u (+ w-screen, sum)    7 degrid 3-D gather tiles
  *   8 grid intermediate transpose                9 degrid intermediate transpose
+ *  10 grid values from a shared binning (grid_visibilities_prepared)
+ * grid_prepare's binning is timed as stage 4 (it is the degridding binning).
  * wsg_stage_times() waits for the recorded events, writes the summed
  * milliseconds and the number of timed sections of the first n stages (one per
  * layer pass; stage 7 one more for the final sum of parts; either pointer may
  * be NULL), clears the record and returns WSG_NSTAGES (or < 0 on error).
  */
-#define WSG_NSTAGES 10
+#define WSG_NSTAGES 11
 void wsg_stage_timing(int enable);
 int wsg_stage_times(double* ms, int* launches, int n);
 

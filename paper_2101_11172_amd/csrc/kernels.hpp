@@ -328,6 +328,27 @@ __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __res
     }
 }
 
+// Gridding records from the degridding records of a shared binning (the fold,
+// coordinates, support boxes and phase depend on uvw alone): record i takes the
+// visibility it names, conjugated when folded (Sec. 5.4), times e^{+i 2 pi w
+// (n0 - 1)}, the conjugate of the degridding phase it holds (Alg. 5 step 2 and
+// Alg. 6 step 5 apply one phase with opposite signs).  The product is formed in
+// FP64.  n_rec: the number of records (device), at most M.
+template <typename R>
+__global__ void k_rec_values(const Rec<R>* __restrict__ rec, const uint32_t* __restrict__ n_rec, size_t M,
+                             const cpx<R>* __restrict__ vis, Rec<R>* __restrict__ out) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= M || i >= size_t(*n_rec)) return;
+    Rec<R> r = rec[i];
+    const cpx<R> V = vis[r.idx & 0x7fffffffu];
+    const double vx = double(V.x), vy = (r.idx & 0x80000000u) ? -double(V.y) : double(V.y);
+    const double co = double(r.v[0]), sn = -double(r.v[1]);
+    r.v[0] = R(vx * co - vy * sn);
+    r.v[1] = R(vx * sn + vy * co);
+    r.idx = 0;
+    out[i] = r;
+}
+
 // Second-level sort and touch classes.  With B = 17 - W, a record whose first
 // support index inside its tile is >= B along an axis also reaches the next
 // tile along that axis (W <= 16: never the one after).  Its touch class is the

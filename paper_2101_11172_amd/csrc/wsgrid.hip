@@ -93,7 +93,7 @@ thread_local std::vector<StageEvent> g_events;
 namespace wsg {
 
 StageMark::StageMark(hipStream_t s_, int st) : s(s_), stage(st) {
-    static_assert(WSG_NSTAGES == 10, "stage ids are listed in wsgrid.h");
+    static_assert(WSG_NSTAGES == 11, "stage ids are listed in wsgrid.h");
     if (g_timing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
 }
 
@@ -127,6 +127,12 @@ struct wsg_plan {
     mutable std::mutex last_mu;
     mutable const void* last_ws = nullptr;
     mutable void* last_stream = nullptr;
+    // the binning kept by grid_prepare: its workspace, size, precision and
+    // per-channel visibility counts (prep_ws null: none)
+    mutable const void* prep_ws = nullptr;
+    mutable size_t prep_bytes = 0;
+    mutable int prep_prec = -1;
+    mutable std::vector<int64_t> prep_M;
 
     int nbins() const { return nbr * nbs * nbt; }
 };
@@ -243,7 +249,7 @@ __global__ void k_set_chan(ChanArgs ca, int nch, long long* __restrict__ coff, i
 // nch channels' visibility counts (host); *M receives their sum.
 int check_call(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* Mc, int64_t* M, const double* uvw,
                const void* a, bool a_empty_ok, const void* b, bool b_empty_ok, void* ws, size_t ws_bytes,
-               Layout* L) {
+               Layout* L, bool uvw_needed = true) {
     if (!plan) return fail(WSG_EINVAL, "null plan");
     if (prec != WSG_F32 && prec != WSG_F64) return fail(WSG_EINVAL, "prec must be WSG_F32 or WSG_F64");
     if (nch < 1 || nch > kMaxChannels) return fail(WSG_EINVAL, "channels must be in [1, 64]");
@@ -256,7 +262,7 @@ int check_call(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* Mc, 
     if (tot > 0x7fffffffLL) return fail(WSG_EINVAL, "total M must be below 2^31");
     *M = tot;
     if ((long long)nch * plan->nbins() > kMaxBins) return fail(WSG_EINVAL, "too many tiles over the channels");
-    if (tot > 0 && !uvw) return fail(WSG_EINVAL, "null uvw pointer");
+    if (uvw_needed && tot > 0 && !uvw) return fail(WSG_EINVAL, "null uvw pointer");
     if (!a && (tot > 0 || !a_empty_ok)) return fail(WSG_EINVAL, "null visibility/image pointer");
     if (!b && (tot > 0 || !b_empty_ok)) return fail(WSG_EINVAL, "null output pointer");
     if (!ws) return fail(WSG_EINVAL, "null workspace");
@@ -272,15 +278,16 @@ int check_call(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* Mc, 
     return WSG_OK;
 }
 
+// Binning (Alg. 5 step 2, Alg. 6 steps 4-5 preprocessing; Sec. 5.4 fold):
+// records binned by tile and sorted by touch class into `rec`, the class
+// starts, the occupancy marks and the ordered tile list.  Grid records carry the
+// phase-rotated visibility, degrid records the phase and the visibility index.
 template <typename R>
-int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const double* uvw, const void* in, void* out,
-        void* ws, const Layout& L, hipStream_t s) {
+void bin_stage(const wsg_plan* plan, bool grid, int stage, const int64_t* Mc, const double* uvw, const void* in,
+               void* ws, const Layout& L, hipStream_t s) {
     DevParams P = dev_params(plan);
     P.nch = L.nch;
     char* w = static_cast<char*>(ws);
-    auto* stack = reinterpret_cast<cpx<R>*>(w + L.stack);
-    auto* inter = reinterpret_cast<cpx<R>*>(w + L.inter);
-    auto* inter2 = reinterpret_cast<cpx<R>*>(w + L.inter2);
     auto* rec_bin = reinterpret_cast<Rec<R>*>(w + L.rec2);   // binned, unordered within a bin
     auto* rec = reinterpret_cast<Rec<R>*>(w + L.rec);        // binned and sorted within each bin
     auto* count = reinterpret_cast<uint32_t*>(w + L.count);
@@ -295,11 +302,6 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
     auto* coff = reinterpret_cast<long long*>(w + L.chan);
     auto* cblk = reinterpret_cast<int*>(w + L.chan + al256(sizeof(long long) * (kMaxChannels + 1)));
     auto* skipped = reinterpret_cast<uint32_t*>(w + L.skipped);
-    const bool f64 = sizeof(R) == 8;
-    const R* coef = f64 ? reinterpret_cast<const R*>(plan->poly64) : reinterpret_cast<const R*>(plan->poly32);
-    const R* coefz = f64 ? reinterpret_cast<const R*>(plan->polyz64) : reinterpret_cast<const R*>(plan->polyz32);
-    const R* corr = f64 ? reinterpret_cast<const R*>(plan->corr64) : reinterpret_cast<const R*>(plan->corr32);
-    const cpx<R>* tw = f64 ? reinterpret_cast<const cpx<R>*>(plan->tw64) : reinterpret_cast<const cpx<R>*>(plan->tw32);
 
     // channel table: visibility offsets and binning blocks (one channel per block)
     ChanArgs ca{};
@@ -309,7 +311,7 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
     }
     const unsigned vblocks = unsigned(ca.blk[L.nch]);
     {
-        StageMark mark(s, grid ? 0 : 4);
+        StageMark mark(s, stage);
         hipLaunchKernelGGL(k_set_chan, dim3(1), dim3(128), 0, s, ca, L.nch, coff, cblk);
         fill<uint32_t>(count, size_t(L.nbins), 0u, s);
         fill<uint32_t>(cursor, size_t(L.nbins), 0u, s);
@@ -339,6 +341,31 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
         hipLaunchKernelGGL(k_tile_list, dim3((L.nbins + 255) / 256), dim3(256), 0, s, (const uint8_t*)occ,
                            (const uint32_t*)tpos, L.nbins, tlist);
     }
+}
+
+// Layer passes over the binned records `rec` (grid: scatter, transforms,
+// w-screen and correction into `out`; degrid: transforms and gather from `in`,
+// then the per-visibility finish into `out`).
+template <typename R>
+int pass_stage(const wsg_plan* plan, bool grid, const Rec<R>* rec, int64_t M, const void* in, void* out, void* ws,
+               const Layout& L, hipStream_t s) {
+    DevParams P = dev_params(plan);
+    P.nch = L.nch;
+    char* w = static_cast<char*>(ws);
+    auto* stack = reinterpret_cast<cpx<R>*>(w + L.stack);
+    auto* inter = reinterpret_cast<cpx<R>*>(w + L.inter);
+    auto* inter2 = reinterpret_cast<cpx<R>*>(w + L.inter2);
+    auto* start = reinterpret_cast<uint32_t*>(w + L.start);
+    auto* cls = reinterpret_cast<uint32_t*>(w + L.cls);
+    auto* occ = reinterpret_cast<uint8_t*>(w + L.occ);
+    auto* rows = reinterpret_cast<uint8_t*>(w + L.rows);
+    auto* tpos = reinterpret_cast<uint32_t*>(w + L.tpos);
+    auto* tlist = reinterpret_cast<uint32_t*>(w + L.tlist);
+    const bool f64 = sizeof(R) == 8;
+    const R* coef = f64 ? reinterpret_cast<const R*>(plan->poly64) : reinterpret_cast<const R*>(plan->poly32);
+    const R* coefz = f64 ? reinterpret_cast<const R*>(plan->polyz64) : reinterpret_cast<const R*>(plan->polyz32);
+    const R* corr = f64 ? reinterpret_cast<const R*>(plan->corr64) : reinterpret_cast<const R*>(plan->corr32);
+    const cpx<R>* tw = f64 ? reinterpret_cast<const cpx<R>*>(plan->tw64) : reinterpret_cast<const cpx<R>*>(plan->tw32);
     // Layer passes over the virtual layer axis (channel c's layers start at
     // c nbt kTileT): the stack and FFT buffers hold L.pass_layers layers at a
     // time.  Grid: each pass scatters into its tiles and transforms them; a
@@ -382,6 +409,32 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
     }
     WSG_HIP(hipGetLastError());
     return WSG_OK;
+}
+
+template <typename R>
+int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const double* uvw, const void* in, void* out,
+        void* ws, const Layout& L, hipStream_t s) {
+    bin_stage<R>(plan, grid, grid ? 0 : 4, Mc, uvw, grid ? in : nullptr, ws, L, s);
+    return pass_stage<R>(plan, grid, reinterpret_cast<const Rec<R>*>(static_cast<char*>(ws) + L.rec), M, in, out,
+                         ws, L, s);
+}
+
+// Gridding from a shared binning: degrid records -> gridding records in the
+// unsorted-record buffer (free after the sort), then the layer passes on them.
+template <typename R>
+int run_prepared(const wsg_plan* plan, bool grid, int64_t M, const void* in, void* out, void* ws, const Layout& L,
+                 hipStream_t s) {
+    char* w = static_cast<char*>(ws);
+    const auto* rec = reinterpret_cast<const Rec<R>*>(w + L.rec);
+    if (!grid) return pass_stage<R>(plan, false, rec, M, in, out, ws, L, s);
+    auto* grec = reinterpret_cast<Rec<R>*>(w + L.rec2);
+    if (M > 0) {
+        StageMark mark(s, 10);
+        hipLaunchKernelGGL(k_rec_values<R>, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, rec,
+                           reinterpret_cast<const uint32_t*>(w + L.start) + L.nbins, size_t(M),
+                           static_cast<const cpx<R>*>(in), grec);
+    }
+    return pass_stage<R>(plan, true, grec, M, in, out, ws, L, s);
 }
 
 template <typename T>
@@ -449,10 +502,13 @@ int build_tables(wsg_plan* p) {
     return WSG_OK;
 }
 
-void remember_call(const wsg_plan* p, const void* ws, void* stream) {
+// Every call records its workspace and stream; a call that is not a
+// prepared one overwrites the binning grid_prepare left in that workspace.
+void remember_call(const wsg_plan* p, const void* ws, void* stream, bool keeps_binning = false) {
     std::lock_guard<std::mutex> g(p->last_mu);
     p->last_ws = ws;
     p->last_stream = stream;
+    if (!keeps_binning && p->prep_ws == ws) p->prep_ws = nullptr;
 }
 
 void free_tables(wsg_plan* p) {
@@ -696,6 +752,71 @@ int degrid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, cons
     remember_call(plan, ws, stream);
     return prec == WSG_F32 ? run<float>(plan, false, M, tot, uvw, image, vis, ws, L, s)
                            : run<double>(plan, false, M, tot, uvw, image, vis, ws, L, s);
+}
+
+int grid_prepare(const wsg_plan* plan, wsg_prec prec, int nch, const int64_t* M, const double* uvw, void* ws,
+                 size_t ws_bytes, void* stream) {
+    Layout L;
+    int64_t tot = 0;
+    int rc = check_call(plan, prec, nch, M, &tot, uvw, uvw, true, ws, true, ws, ws_bytes, &L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    remember_call(plan, ws, stream);
+    if (prec == WSG_F32)
+        bin_stage<float>(plan, false, 4, M, uvw, nullptr, ws, L, s);
+    else
+        bin_stage<double>(plan, false, 4, M, uvw, nullptr, ws, L, s);
+    WSG_HIP(hipGetLastError());
+    std::lock_guard<std::mutex> g(plan->last_mu);
+    plan->prep_ws = ws;
+    plan->prep_bytes = ws_bytes;
+    plan->prep_prec = int(prec);
+    plan->prep_M.assign(M, M + nch);
+    return WSG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// A call on the binning grid_prepare left in `ws`: checks that it is there
+// (same workspace, size and precision) and runs one direction on it.
+int call_prepared(bool grid, const wsg_plan* plan, wsg_prec prec, const void* in, void* out, void* ws,
+                  size_t ws_bytes, void* stream) {
+    if (!plan) return fail(WSG_EINVAL, "null plan");
+    std::vector<int64_t> Mc;
+    {
+        std::lock_guard<std::mutex> g(plan->last_mu);
+        if (!ws || plan->prep_ws != ws || plan->prep_bytes != ws_bytes || plan->prep_prec != int(prec))
+            return fail(WSG_EINVAL, "no binning of this plan and precision in this workspace: call grid_prepare "
+                                    "first (any other call on the workspace replaces it)");
+        Mc = plan->prep_M;
+    }
+    Layout L;
+    int64_t tot = 0;
+    int rc = grid ? check_call(plan, prec, int(Mc.size()), Mc.data(), &tot, nullptr, in, true, out, false, ws,
+                               ws_bytes, &L, false)
+                  : check_call(plan, prec, int(Mc.size()), Mc.data(), &tot, nullptr, in, false, out, true, ws,
+                               ws_bytes, &L, false);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    remember_call(plan, ws, stream, true);
+    return prec == WSG_F32 ? run_prepared<float>(plan, grid, tot, in, out, ws, L, s)
+                           : run_prepared<double>(plan, grid, tot, in, out, ws, L, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int grid_visibilities_prepared(const wsg_plan* plan, wsg_prec prec, const void* vis, void* dirty, void* ws,
+                               size_t ws_bytes, void* stream) {
+    return call_prepared(true, plan, prec, vis, dirty, ws, ws_bytes, stream);
+}
+
+int degrid_visibilities_prepared(const wsg_plan* plan, wsg_prec prec, const void* image, void* vis, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    return call_prepared(false, plan, prec, image, vis, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -56,6 +56,13 @@ _SIGNATURES = {
     "degrid_visibilities_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int64_p,
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_size_t, ctypes.c_void_p]),
+    "grid_prepare": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int64_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "grid_visibilities_prepared": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "degrid_visibilities_prepared": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                                    ctypes.c_void_p]),
     "grid_workspace_bytes_batch": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                                      ctypes.c_int]),
     "grid_visibilities_multi": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, _c_int64_p,
@@ -226,6 +233,22 @@ def degrid_visibilities_batch(plan: int, prec: int, M, uvw_ptr: int, image_ptr: 
                                          ws_bytes, stream), "degrid_visibilities_batch")
 
 
+def grid_prepare(plan: int, prec: int, M, uvw_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _err(lib().grid_prepare(plan, prec, len(M), _counts(M), uvw_ptr, ws_ptr, ws_bytes, stream), "grid_prepare")
+
+
+def grid_visibilities_prepared(plan: int, prec: int, vis_ptr: int, dirty_ptr: int, ws_ptr: int, ws_bytes: int,
+                               stream: int) -> None:
+    _err(lib().grid_visibilities_prepared(plan, prec, vis_ptr, dirty_ptr, ws_ptr, ws_bytes, stream),
+         "grid_visibilities_prepared")
+
+
+def degrid_visibilities_prepared(plan: int, prec: int, image_ptr: int, vis_ptr: int, ws_ptr: int, ws_bytes: int,
+                                 stream: int) -> None:
+    _err(lib().degrid_visibilities_prepared(plan, prec, image_ptr, vis_ptr, ws_ptr, ws_bytes, stream),
+         "degrid_visibilities_prepared")
+
+
 def _plan_array(plans) -> ctypes.Array:
     return (ctypes.c_void_p * len(plans))(*[int(p) for p in plans])
 
@@ -292,7 +315,7 @@ def wsg_plan_params(N: int, L: float, W: int, x0: float, wmax: float, z_offset: 
 
 
 STAGES = ("grid_bin", "grid_tiles", "grid_fft_v", "grid_fft_u", "degrid_bin", "degrid_fft_p", "degrid_fft_q",
-          "degrid_tiles", "grid_transpose", "degrid_transpose")
+          "degrid_tiles", "grid_transpose", "degrid_transpose", "grid_values")
 
 
 def wsg_stage_timing(enable: bool) -> None:
@@ -344,6 +367,7 @@ class Plan:
         self.max_workspace_bytes = max_workspace_bytes
         self.info = grid_plan_info(self._p)
         self._ws = {}
+        self._prep = {}        # prec -> (M, channels, workspace) of the binning kept by prepare()
 
     def close(self):
         if getattr(self, "_p", None):
@@ -357,6 +381,9 @@ class Plan:
             pass
 
     def workspace(self, prec: int, M: int, nch: int = 1) -> torch.Tensor:
+        """The workspace of a plain or prepare() call in this precision (such a
+        call replaces the binning a previous prepare() left there)."""
+        self._prep.pop(prec, None)
         need = grid_workspace_bytes_batch(self._p, prec, nch, M)
         if self.max_workspace_bytes is not None and need > self.max_workspace_bytes:
             need = max(grid_workspace_bytes_batch(self._p, prec, nch, M, True), int(self.max_workspace_bytes))
@@ -455,6 +482,74 @@ class Plan:
                                   ws.data_ptr(), ws.numel(), torch.cuda.current_stream(self.device).cuda_stream)
         return out
 
+    # ---- one binning shared by gridding and degridding (grid_prepare) ----
+
+    def prepare(self, uvw: torch.Tensor, dtype=torch.float32, counts=None) -> None:
+        """Bin uvw once for the prepared calls that follow (precision of dtype:
+        float32/complex64 or float64/complex128).  counts: channel counts as for
+        grid_batch (default one channel).  Any plain call of this plan in that
+        precision replaces the binning."""
+        M = self._check_uvw(uvw)
+        counts = [M] if counts is None else self.check_batch(uvw, counts)[1]
+        prec = _PREC[dtype]
+        ws = self.workspace(prec, M, len(counts))
+        grid_prepare(self._p, prec, counts, uvw.data_ptr(), ws.data_ptr(), ws.numel(),
+                     torch.cuda.current_stream(self.device).cuda_stream)
+        self._prep[prec] = (M, len(counts), ws, self._uvw_key(uvw, counts))
+
+    @staticmethod
+    def _uvw_key(uvw: torch.Tensor, counts) -> tuple:
+        return (uvw.data_ptr(), uvw._version, tuple(uvw.shape), tuple(counts))
+
+    def _prepared(self, prec: int):
+        if prec not in self._prep or self._ws.get(prec) is not self._prep[prec][2]:
+            raise RuntimeError("no prepared binning in this precision: call prepare(uvw) first")
+        return self._prep[prec][:3]
+
+    def prepared_for(self, dtype, uvw: torch.Tensor | None = None, counts=None) -> bool:
+        """Whether a binning from prepare() is held for this precision (and, if
+        given, for this uvw tensor, unmodified since)."""
+        prec = _PREC[dtype]
+        if prec not in self._prep or self._ws.get(prec) is not self._prep[prec][2]:
+            return False
+        return uvw is None or self._prep[prec][3] == self._uvw_key(uvw, [uvw.shape[0]] if counts is None else counts)
+
+    def grid_prepared(self, vis: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Dirty map(s) of the prepared visibilities: [N, N] (or [channels, N, N])."""
+        prec = _PREC[vis.dtype] if vis.dtype in (torch.complex64, torch.complex128) else None
+        if prec is None:
+            raise ValueError("vis must be complex64 or complex128")
+        M, nch, ws = self._prepared(prec)
+        if vis.shape != (M,) or not vis.is_contiguous() or vis.device != self.device:
+            raise ValueError("vis must be a contiguous [M] tensor of the prepared visibilities on the device")
+        rdt = torch.float32 if prec == WSG_F32 else torch.float64
+        shape = (self.N, self.N) if nch == 1 else (nch, self.N, self.N)
+        if out is None:
+            out = torch.empty(shape, dtype=rdt, device=self.device)
+        elif out.dtype != rdt or out.shape != shape or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or shape")
+        grid_visibilities_prepared(self._p, prec, vis.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                   torch.cuda.current_stream(self.device).cuda_stream)
+        return out
+
+    def degrid_prepared(self, image: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Model visibilities [M] of the prepared uvw from image(s) [N, N] (or [channels, N, N])."""
+        if image.dtype not in (torch.float32, torch.float64):
+            raise ValueError("image must be float32 or float64")
+        prec = _PREC[image.dtype]
+        M, nch, ws = self._prepared(prec)
+        shape = (self.N, self.N) if nch == 1 else (nch, self.N, self.N)
+        if image.shape != shape or not image.is_contiguous() or image.device != self.device:
+            raise ValueError(f"image must be a contiguous {shape} tensor on the plan's device")
+        cdt = torch.complex64 if prec == WSG_F32 else torch.complex128
+        if out is None:
+            out = torch.empty(M, dtype=cdt, device=self.device)
+        elif out.dtype != cdt or out.shape != (M,) or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or shape")
+        degrid_visibilities_prepared(self._p, prec, image.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                     torch.cuda.current_stream(self.device).cuda_stream)
+        return out
+
     def skipped(self, prec: int) -> int:
         ws = self._ws[prec]
         return grid_skipped(self._p, ws.data_ptr(), torch.cuda.current_stream(self.device).cuda_stream)
@@ -547,7 +642,9 @@ class DegridFn(torch.autograd.Function):
     """Model visibilities of a real image as a differentiable torch operation.
 
     forward: degrid_visibilities (Algorithm 6).  backward: grid_visibilities
-    (Algorithm 5) applied to the incoming gradient.  For a real image f and
+    (Algorithm 5) applied to the incoming gradient.  The forward bins uvw once
+    (grid_prepare) and the backward reuses that binning while the plan still
+    holds it for the same, unmodified uvw (else it bins again).  For a real image f and
     vis = A f, torch's gradient for a complex output is g = dL/dRe(vis) +
     i dL/dIm(vis), so dL/df = Re(A^H g); the gridding operator returns exactly
     Re(A^H g), the two being adjoint (Sec. 3.1-3.2, eq. gridded-dirty-map).
@@ -559,12 +656,17 @@ class DegridFn(torch.autograd.Function):
     def forward(ctx, image: torch.Tensor, plan: "Plan", uvw: torch.Tensor) -> torch.Tensor:
         ctx.plan = plan
         ctx.save_for_backward(uvw)
-        return plan.degrid(uvw, image.contiguous())
+        image = image.contiguous()
+        plan.prepare(uvw, image.dtype)
+        return plan.degrid_prepared(image)
 
     @staticmethod
     def backward(ctx, grad_vis: torch.Tensor):
         (uvw,) = ctx.saved_tensors
-        return ctx.plan.grid(uvw, grad_vis.contiguous()), None, None
+        g = grad_vis.contiguous()
+        if ctx.plan.prepared_for(g.dtype, uvw):
+            return ctx.plan.grid_prepared(g), None, None
+        return ctx.plan.grid(uvw, g), None, None
 
 
 def degrid_fn(plan: Plan, uvw: torch.Tensor, image: torch.Tensor) -> torch.Tensor:

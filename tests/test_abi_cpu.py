@@ -71,6 +71,15 @@ def test_probe_and_last_skipped_reject_bad_arguments():
     assert wg.lib().grid_last_skipped(None) == wg.WSG_EINVAL
 
 
+def test_prepared_calls_reject_bad_arguments():
+    # null plans are refused before any device call
+    one = wg._counts([10])
+    assert wg.lib().grid_prepare(None, wg.WSG_F32, 1, one, 4096, 8192, 1 << 20, None) == wg.WSG_EINVAL
+    assert wg.lib().grid_visibilities_prepared(None, wg.WSG_F32, 4096, 8192, 16384, 1 << 20, None) == wg.WSG_EINVAL
+    assert wg.lib().degrid_visibilities_prepared(None, wg.WSG_F64, 4096, 8192, 16384, 1 << 20, None) == wg.WSG_EINVAL
+    assert "null plan" in wg.grid_last_error()
+
+
 @pytest.mark.parametrize("args", [(64, 0.3, 7, 0.25, 3, 0.2, 100.0), (256, 0.4, 7, 0.25, 1, 0.05, 300.0),
                                   (96, 0.4, 5, 1 / 3, 5, 1 / 3, 50.0)])
 @pytest.mark.parametrize("z_offset", [True, False])
