@@ -14,7 +14,7 @@ on all 9,999,360 visibilities, the checks are properties that hold at any size:
   bound: the method's sqrt(3) E (Sec. 6.3) with a factor 2 for FP64, and the
   single-precision target 1e-6 for FP32 at W = 7, x0 = 1/4;
 * the adjoint identity Re <degrid f, V> = <f, grid V> in FP64 (Sec. 3.1-3.2);
-* FP32 against FP64 on the full arrays (spec target 1e-6 at W = 7).
+* FP32 against FP64 on the full arrays (the single-precision target 1e-6 at W = 7).
 """
 import numpy as np
 import pytest
