@@ -768,6 +768,21 @@ __global__ void __launch_bounds__((ScatterCfg<R, W, WZ>::kThreads)) k_grid_tiles
         constexpr int A0 = (W + LPR - 1) / LPR;
         static_assert(WZ <= W, "the w-axis function is at most as wide as the u, v one");
         const int rl = lane & (WB - 1), half = lane / WB;
+        // The lane's coefficients, loaded once into registers when they fit in
+        // 40 of them (else read from global memory at each staging).
+        constexpr bool kRegCoef = A0 * (D + 1) * (SAME ? 1 : 2) * int(sizeof(R)) <= 160;
+        R creg[kRegCoef ? A0 : 1][D + 1], czreg[(kRegCoef && !SAME) ? A0 : 1][D + 1];
+        if constexpr (kRegCoef) {
+#pragma unroll
+            for (int i = 0; i < A0; ++i) {
+                const int a = i + half * A0;
+#pragma unroll
+                for (int k = 0; k <= D; ++k) {
+                    creg[i][k] = coef_g[min(a, W - 1) * (D + 1) + k];
+                    if constexpr (!SAME) czreg[i][k] = coefz_g[min(a, WZ - 1) * (D + 1) + k];
+                }
+            }
+        }
         // the lane's next record: virtual position vn in range g (ranges only
         // move forward as vn grows by WB per round)
         uint32_t vn = q0 + uint32_t(rl);
@@ -790,13 +805,19 @@ __global__ void __launch_bounds__((ScatterCfg<R, W, WZ>::kThreads)) k_grid_tiles
                     const int a = i + half * A0;
                     const R* c = coef_g + min(a, W - 1) * (D + 1);
                     const R* cz = (SAME ? coef_g : coefz_g) + min(a, WZ - 1) * (D + 1);
-                    R hu = c[D], hv = c[D], ht = cz[D];
+                    auto cu = [&](int k) { if constexpr (kRegCoef) return creg[i][k]; else return c[k]; };
+                    auto cw = [&](int k) {
+                        if constexpr (SAME) return cu(k);
+                        else if constexpr (kRegCoef) return czreg[i][k];
+                        else return cz[k];
+                    };
+                    R hu = cu(D), hv = cu(D), ht = cw(D);
 #pragma unroll
                     for (int k = D - 1; k >= 0; --k) {
-                        const R ck = c[k];
+                        const R ck = cu(k);
                         hu = hu * nxt.nu[0] + ck;
                         hv = hv * nxt.nu[1] + ck;
-                        ht = ht * nxt.nu[2] + (SAME ? ck : cz[k]);
+                        ht = ht * nxt.nu[2] + cw(k);
                     }
                     if (a < W) {
                         int ku = pr + a, kv = ps + a;
