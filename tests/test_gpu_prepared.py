@@ -146,3 +146,26 @@ def test_widefield_prepared_step():
     print(f"widefield prepared vs plain: grid {e:.2e}")
     assert torch.equal(d, d_plain) and e <= 1e-6
     plan.close()
+
+
+@pytest.mark.parametrize("variant", [dict(method="original", n_bins=12), dict(Wz=3, z0=0.2), dict(method="no_offset"),
+                                     dict(x0=1 / 3)], ids=["original", "own-w-axis", "no-offset", "x0=1/3"])
+def test_prepared_variants_match_plain(variant):
+    """The shared binning under every planner variant: degrid bit for bit,
+    grid within rounding of the plain calls, both directions against the oracle's
+    adjoint identity."""
+    v = dict(variant)
+    N, L, W, wmax, M = 64, 0.4, 7, 120.0, 2000
+    x0 = v.pop("x0", 0.25)
+    uvw = torch.from_numpy(inputs.uniform_uvw(M, 0.9 * N / (2 * L), wmax, 171)).to(DEV)
+    vis = torch.from_numpy(inputs.random_vis(M, 172)).to(DEV)
+    img = torch.from_numpy(inputs.random_image(N, 173)).to(DEV)
+    plan = wg.Plan(N, L, W, x0, wmax, device=DEV, **v)
+    g_plain, d_plain = plan.grid(uvw, vis).cpu().numpy(), plan.degrid(uvw, img).cpu()
+    plan.prepare(uvw, torch.float64)
+    g, d = plan.grid_prepared(vis).cpu().numpy(), plan.degrid_prepared(img).cpu()
+    assert torch.equal(d, d_plain) and rel(g, g_plain) <= 1e-13
+    lhs = float(torch.real(torch.vdot(vis.cpu(), d)))
+    rhs = float(np.sum(img.cpu().numpy() * g))
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+    plan.close()
