@@ -370,16 +370,35 @@ def channels_multi_main(args) -> int:
         ps.max_workspace_bytes = tuned["workspace_bytes"]
         log(f"autotune: workspace {tuned['workspace_bytes']} bytes, ms by workspace {tuned['ms']}")
 
+    # The step: the channels' uvw binned once (one grid_prepare per size group),
+    # then one gridding and one degridding of all channels on that binning.
     def step():
-        ps.grid(uvw, counts, vis, out=out_img)
-        ps.degrid(uvw, counts, img, out=out_vis)
+        ps.prepare(uvw, counts, torch.float32)
+        ps.grid_prepared(vis, out=out_img)
+        ps.degrid_prepared(img, out=out_vis)
 
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{args.warmup} done")
     ms, stages = timed(step, args.steps)
-    log(f"channels (per-channel sizes): {ms:.3f} ms/step, {M / (ms * 1e-3):.4e} vis/s")
+    log(f"channels (per-channel sizes, one binning per step): {ms:.3f} ms/step, {M / (ms * 1e-3):.4e} vis/s")
+    prep_ws = sum(w.numel() for w in ps._prep_ws)
+    ps._prep_ws, ps._prep = [], None
+    torch.cuda.empty_cache()
+
+    # The same work as two independent multi-plan calls, each binning uvw itself.
+    sep_img, sep_vis = torch.empty_like(out_img), torch.empty_like(out_vis)
+
+    def step_separate():
+        ps.grid(uvw, counts, vis, out=sep_img)
+        ps.degrid(uvw, counts, img, out=sep_vis)
+
+    step_separate()
+    ms_sep, stages_sep = timed(step_separate, args.steps)
+    log(f"channels, separate multi-plan calls: {ms_sep:.3f} ms/step, {M / (ms_sep * 1e-3):.4e} vis/s")
+    grid_rel = float(torch.linalg.vector_norm(out_img.double() - sep_img.double())
+                     / torch.linalg.vector_norm(sep_img.double()))
     result = {
         "metric": "batched channels: visibilities/s grid+degrid, 32 channels, image size per channel",
         "value": M / (ms * 1e-3),
@@ -398,9 +417,16 @@ def channels_multi_main(args) -> int:
                                 f"({sizes.count(1536)} x 1536^2, {sizes.count(2048)} x 2048^2), L={L}, W={W}, "
                                 f"x0={x0}, one plan per size group"),
                    "channels": C, "visibilities": M, "groups": {str(k): v for k, v in groups.items()},
-                   "workspace_bytes": ps.workspace(wsgrid.WSG_F32, counts).numel()},
+                   "workspace_bytes": prep_ws,
+                   "step": "uvw binned once per size group (grid_prepare), then one grid and one degrid of all "
+                           "channels on that binning; separate_calls: grid/degrid_visibilities_multi"},
         "autotune": tuned,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+        "separate_calls": {"value": M / (ms_sep * 1e-3), "ms_per_step": ms_sep,
+                           "workspace_bytes": ps.workspace(wsgrid.WSG_F32, counts).numel(),
+                           "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages_sep.items() if v[1]},
+                           "prepared_vs_separate": {"grid_rel_rms": grid_rel,
+                                                    "degrid_equal": bool(torch.equal(out_vis, sep_vis))}},
     }
     print(json.dumps(result), flush=True)
     for p in plans.values():

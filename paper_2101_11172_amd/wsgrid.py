@@ -571,6 +571,8 @@ class PlanSet:
             raise ValueError("all plans must be on one device")
         self.max_workspace_bytes = max_workspace_bytes
         self._ws = {}
+        self._prep = None          # (prec, M, counts, runs, run sizes) of the binning kept by prepare()
+        self._prep_ws = []         # its workspaces, one per run
 
     def _ptrs(self):
         return [p._p for p in self.plans]
@@ -595,6 +597,100 @@ class PlanSet:
             ws = torch.empty(need, dtype=torch.uint8, device=self.device)
             self._ws[prec] = ws
         return ws
+
+    def _runs(self):
+        """(plan, first channel, end channel) of each run of channels on one plan."""
+        runs = []
+        for c, p in enumerate(self.plans):
+            if runs and runs[-1][0] is p:
+                runs[-1][2] = c + 1
+            else:
+                if any(r[0] is p for r in runs):
+                    raise ValueError("channels sharing a plan must be consecutive")
+                runs.append([p, c, c + 1])
+        return [tuple(r) for r in runs]
+
+    # ---- one binning shared by gridding and degridding (grid_prepare per run) ----
+
+    def prepare(self, uvw: torch.Tensor, counts, dtype=torch.float32) -> None:
+        """Bin the channels' visibilities once, one grid_prepare per run of
+        channels on one plan, each into a workspace of its own (each within
+        max_workspace_bytes when set, but at least the smallest its run accepts;
+        a run's layers go in passes below its full size).  grid_prepared / degrid_prepared then take only values."""
+        M, counts = self._check(uvw, counts)
+        prec = _PREC[dtype]
+        runs = self._runs()
+        ms = [sum(counts[c0:c1]) for _, c0, c1 in runs]
+        full = [grid_workspace_bytes_batch(p._p, prec, c1 - c0, m) for (p, c0, c1), m in zip(runs, ms)]
+        least = [grid_workspace_bytes_batch(p._p, prec, c1 - c0, m, True) for (p, c0, c1), m in zip(runs, ms)]
+        size = full
+        if self.max_workspace_bytes is not None:
+            # each run's workspace within the cap (at least its smallest), as the
+            # shared workspace of grid() is for every run: the runs then take the
+            # same layer passes as there, and the binnings together hold up to
+            # one cap per run
+            cap = int(self.max_workspace_bytes)
+            size = [min(f, max(lo, cap)) for f, lo in zip(full, least)]
+        self._prep = None
+        old = self._prep_ws
+        ws = [old[i] if i < len(old) and old[i].numel() == n else torch.empty(n, dtype=torch.uint8, device=self.device)
+              for i, n in enumerate(size)]
+        self._prep_ws = ws
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        v0 = 0
+        for (p, c0, c1), m, w in zip(runs, ms, ws):
+            grid_prepare(p._p, prec, counts[c0:c1], uvw.data_ptr() + 24 * v0, w.data_ptr(), w.numel(), stream)
+            v0 += m
+        self._prep = (prec, M, counts, runs, ms)
+
+    def _prepared(self, prec: int):
+        if self._prep is None or self._prep[0] != prec:
+            raise RuntimeError("no prepared binning in this precision: call prepare(uvw, counts) first")
+        return self._prep
+
+    def grid_prepared(self, vis: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Packed dirty maps of the prepared visibilities (values in channel order)."""
+        if vis.dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("vis must be complex64 or complex128")
+        prec, M, counts, runs, ms = self._prepared(_PREC[vis.dtype])
+        if vis.shape != (M,) or not vis.is_contiguous() or vis.device != self.device:
+            raise ValueError("vis must be a contiguous [M] tensor of the prepared visibilities on the device")
+        rdt = torch.float32 if prec == WSG_F32 else torch.float64
+        if out is None:
+            out = torch.empty(self.map_elements(), dtype=rdt, device=self.device)
+        elif out.dtype != rdt or out.shape != (self.map_elements(),) or not out.is_contiguous():
+            raise ValueError("out must be the packed maps")
+        cs, rs = vis.element_size(), out.element_size()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        v0, m0 = 0, 0
+        for (p, c0, c1), m, w in zip(runs, ms, self._prep_ws):
+            grid_visibilities_prepared(p._p, prec, vis.data_ptr() + cs * v0, out.data_ptr() + rs * m0, w.data_ptr(),
+                                       w.numel(), stream)
+            v0 += m
+            m0 += (c1 - c0) * p.N * p.N
+        return out
+
+    def degrid_prepared(self, image: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Model visibilities of the prepared uvw from the packed maps."""
+        if image.dtype not in (torch.float32, torch.float64):
+            raise ValueError("image must be float32 or float64")
+        prec, M, counts, runs, ms = self._prepared(_PREC[image.dtype])
+        if image.shape != (self.map_elements(),) or not image.is_contiguous() or image.device != self.device:
+            raise ValueError("image must be the packed maps on the plans' device")
+        cdt = torch.complex64 if prec == WSG_F32 else torch.complex128
+        if out is None:
+            out = torch.empty(M, dtype=cdt, device=self.device)
+        elif out.dtype != cdt or out.shape != (M,) or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or shape")
+        cs, rs = out.element_size(), image.element_size()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        v0, m0 = 0, 0
+        for (p, c0, c1), m, w in zip(runs, ms, self._prep_ws):
+            degrid_visibilities_prepared(p._p, prec, image.data_ptr() + rs * m0, out.data_ptr() + cs * v0,
+                                         w.data_ptr(), w.numel(), stream)
+            v0 += m
+            m0 += (c1 - c0) * p.N * p.N
+        return out
 
     def _check(self, uvw, counts):
         counts = [int(c) for c in counts]

@@ -184,3 +184,32 @@ def test_multi_plan_channels_match_single_and_oracle():
         bad.grid(uvw_all[:30].contiguous(), [10, 10, 10], torch.zeros(30, dtype=torch.complex64, device=DEV))
     for p in plans.values():
         p.close()
+
+
+@pytest.mark.parametrize("cap", [None, 1], ids=["full", "smallest"])
+def test_multi_plan_shared_binning_matches_multi(cap):
+    """PlanSet.prepare + grid_prepared / degrid_prepared (one grid_prepare per
+    run of channels on one plan, each run in its own workspace) against the
+    plain multi-plan calls: degrid bit for bit, grid within rounding; with the
+    smallest workspaces the runs go in layer passes."""
+    L, W, x0 = 0.3, 7, 0.25
+    spec = [(64, 80.0), (64, 80.0), (96, 300.0), (96, 300.0)]
+    counts = [700, 300, 0, 1200]
+    plans = {key: wg.Plan(key[0], L, W, x0, key[1], device=DEV) for key in sorted(set(spec))}
+    uvw = torch.from_numpy(np.concatenate([inputs.uniform_uvw(m, 0.9 * n / (2 * L), wmax, 330 + c)
+                                           for c, ((n, wmax), m) in enumerate(zip(spec, counts))])).to(DEV)
+    vis = torch.from_numpy(inputs.random_vis(sum(counts), 340)).to(DEV)
+    img = torch.cat([torch.from_numpy(inputs.random_image(n, 350 + c)).reshape(-1) for c, (n, _) in enumerate(spec)]).to(DEV)
+    ps = wg.PlanSet([plans[k] for k in spec], max_workspace_bytes=cap)
+    g_m, d_m = ps.grid(uvw, counts, vis).cpu().numpy(), ps.degrid(uvw, counts, img).cpu()
+    ps.prepare(uvw, counts, torch.float64)
+    g_p, d_p = ps.grid_prepared(vis).cpu().numpy(), ps.degrid_prepared(img).cpu()
+    assert torch.equal(d_p, d_m)
+    assert rel(g_p, g_m) <= 1e-13
+    if cap is not None:
+        assert any(wg.grid_layers_per_pass(p._p, wg.WSG_F64, c1 - c0, sum(counts[c0:c1]), w.numel())
+                   < p.info["n_layers"] * (c1 - c0) for (p, c0, c1), w in zip(ps._runs(), ps._prep_ws))
+    with pytest.raises(RuntimeError, match="prepare"):
+        ps.grid_prepared(vis.to(torch.complex64))          # binned in FP64 only
+    for p in plans.values():
+        p.close()
