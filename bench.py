@@ -604,8 +604,10 @@ def main() -> int:
                     help="lowcost: the wide-field geometry at W=4, x0=0.5; widefield3: at x0=1/3 (N'=3072); "
                          "imaging: one differentiable-imaging gradient step per step (4096^2, 50M visibilities); "
                          "channels: one batched grid + degrid of 32 channels per step")
-    ap.add_argument("--max-workspace-gb", type=float, default=96.0,
-                    help="imaging and channels: workspace cap (layer passes)")
+    ap.add_argument("--max-workspace-gb", type=float, default=None,
+                    help="imaging and channels: workspace cap (layer passes); default 64 for imaging "
+                         "(5 passes measured fastest: 40-64 GB 159.7-160.0 ms, 96 GB 161.4, 160 GB 165.7, "
+                         "one pass 179.2), 96 for channels")
     ap.add_argument("--one-plan", action="store_true",
                     help="channels: one 2048^2 plan for every channel (instead of an image size per channel)")
     ap.add_argument("--autotune", action="store_true",
@@ -615,6 +617,8 @@ def main() -> int:
         print("bench.py measures one GPU: the path is built and measured on a single MI355X "
               "(multi-GPU sharding over w-layers is a design, not a measured run)", file=sys.stderr)
         return 2
+    if args.max_workspace_gb is None:
+        args.max_workspace_gb = 64.0 if args.workload == "imaging" else 96.0
     if args.workload == "imaging":
         return imaging_main(args)
     if args.workload == "channels":
