@@ -116,9 +116,9 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def workload_key(name: str, N: int, W: int, x0: float, M: int, n_layers: int) -> str:
-    """Names the workload a counter run was taken on (counters hold for that one only)."""
-    return f"{name} N={N} W={W} x0={x0:.6g} M={M} layers={n_layers}"
+def workload_key(name: str, N: int, W: int, x0: float, M: int, n_layers: int, pass_layers: int) -> str:
+    """Names the workload and layer-pass size a counter run was taken on (counters hold for that one only)."""
+    return f"{name} N={N} W={W} x0={x0:.6g} M={M} layers={n_layers} pass={pass_layers}"
 
 
 def counters(key: str):
@@ -307,6 +307,18 @@ def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int, ws: d
         tab[name] = {"ms": per, "launches_per_call": n / calls, "alg_bytes": nbytes,
                      "alg_GBps": nbytes / (per * 1e-3) / 1e9}
     return tab
+
+
+def timed_plain(step, steps: int) -> float:
+    """Milliseconds per step over `steps` steps, without stage events."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
 
 
 def timed(step, steps: int):
@@ -610,6 +622,9 @@ def main() -> int:
                          "one pass 179.2), 96 for channels")
     ap.add_argument("--one-plan", action="store_true",
                     help="channels: one 2048^2 plan for every channel (instead of an image size per channel)")
+    ap.add_argument("--pass-layers", type=int, default=None,
+                    help="widefield, lowcost, widefield3: layers per pass (0: all in one pass); default: the "
+                         "autotuner times every pass size and takes the fastest")
     ap.add_argument("--autotune", action="store_true",
                     help="channels: choose the layers per pass within the cap by timing (autotune.py) first")
     args = ap.parse_args()
@@ -655,6 +670,19 @@ def main() -> int:
     uvw = torch.from_numpy(w["uvw"]).to(dev)
     vis32 = torch.from_numpy(w["vis"]).to(dev)
     img32 = torch.from_numpy(inputs.random_image(N, 5).astype(np.float32)).to(dev)
+
+    # layer-pass size: timed by the autotuner over every pass size (one plain
+    # grid + degrid each), or as given; the workspace is the smallest that holds it
+    from paper_2101_11172_amd.autotune import tune_pass_layers, workspace_for_pass_layers
+    tuned = None
+    if args.pass_layers is None:
+        tuned = tune_pass_layers(plan, uvw, [M], vis32, img32.reshape(1, N, N), 1 << 62, repeats=3,
+                                 every_pass_size=True)
+        pass_layers = tuned["pass_layers"]
+        log(f"autotune: {pass_layers} layers per pass, ms by pass size {tuned['ms']}")
+    else:
+        pass_layers = min(nl, args.pass_layers) if args.pass_layers > 0 else nl
+    plan.max_workspace_bytes = ws32_bytes = workspace_for_pass_layers(plan, wsgrid.WSG_F32, 1, M, pass_layers)
     out_img32 = torch.empty((N, N), dtype=torch.float32, device=dev)
     out_vis32 = torch.empty(M, dtype=torch.complex64, device=dev)
 
@@ -680,11 +708,13 @@ def main() -> int:
         step32_separate()
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{args.warmup} done")
-    ms32, stages32 = timed(step32, args.steps)
+    ms32 = timed_plain(step32, args.steps)
+    _, stages32 = timed(step32, args.steps)
     log(f"fp32: {ms32:.3f} ms/step, {M / (ms32 * 1e-3):.4e} vis/s (one binning per step)")
     tab32 = stage_table(stages32, False, M, N, Np, nl, ws, args.steps)
     skipped = plan.skipped(wsgrid.WSG_F32)
-    ms_sep, stages_sep = timed(step32_separate, args.steps)
+    ms_sep = timed_plain(step32_separate, args.steps)
+    _, stages_sep = timed(step32_separate, args.steps)
     log(f"fp32 separate calls: {ms_sep:.3f} ms/step, {M / (ms_sep * 1e-3):.4e} vis/s")
     separate = {"value": M / (ms_sep * 1e-3), "ms_per_step": ms_sep,
                 "stages": stage_table(stages_sep, False, M, N, Np, nl, ws, args.steps),
@@ -702,8 +732,10 @@ def main() -> int:
             plan.grid_prepared(vis64, out=out_img64)
             plan.degrid_prepared(img64, out=out_vis64)
 
+        plan.max_workspace_bytes = workspace_for_pass_layers(plan, wsgrid.WSG_F64, 1, M, pass_layers)
         step64()
-        ms64, stages64 = timed(step64, args.fp64_steps)
+        ms64 = timed_plain(step64, args.fp64_steps)
+        _, stages64 = timed(step64, args.fp64_steps)
         log(f"fp64: {ms64:.3f} ms/step, {M / (ms64 * 1e-3):.4e} vis/s")
         fp64 = {"value": M / (ms64 * 1e-3), "ms_per_step": ms64,
                 "stages": stage_table(stages64, True, M, N, Np, nl, ws, args.fp64_steps)}
@@ -719,15 +751,20 @@ def main() -> int:
     dom = max(tab32, key=lambda k: tab32[k]["ms"])
     d = tab32[dom]
     achievable = probe["GBps"] if probe else None
-    key = workload_key(args.workload + ("-no-z-offset" if args.no_z_offset else ""), N, W, x0, M, nl)
+    key = workload_key(args.workload + ("-no-z-offset" if args.no_z_offset else ""), N, W, x0, M, nl, pass_layers)
+    per_launch = traffic_for(dom, "f32", key)          # counters: average HBM bytes per launch
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic_for(dom, "f32", key),
+                "frac": d["alg_GBps"] / HBM_PEAK_GBS,
+                "traffic": per_launch * d["launches_per_call"] if per_launch is not None else None,
                 "achievable": achievable, "frac_of_achievable": d["alg_GBps"] / achievable if achievable else None,
                 "alg_bytes_per_call": d["alg_bytes"], "ms_per_call": d["ms"],
                 "launches_per_call": d["launches_per_call"]}
     issue = issue_for(dom, "f32", key)
     if issue:
-        roofline["issue"] = {**issue, "valu_issue_frac": issue["valu_issue_ms"] / d["ms"]}
+        n = d["launches_per_call"]
+        roofline["issue"] = {"valu_instr_per_call": issue["valu_instr_per_launch"] * n,
+                             "valu_issue_ms": issue["valu_issue_ms"] * n,
+                             "valu_issue_frac": issue["valu_issue_ms"] * n / d["ms"]}
     total_alg = sum(stage_bytes(s, M, N, Np, nl, False, ws) for s in tab32)
     result = {
         "metric": (f"visibilities/s grid+degrid at W={W},x0={x0:g}, FP32 vs FP64"
@@ -751,7 +788,8 @@ def main() -> int:
                                 f"uvw scaled to a Nyquist-sampled image), {nl} w-layers, N'={Np}"
                                 + (", planner without z offset" if args.no_z_offset else "")),
                    "N": N, "L": L, "W": W, "x0": x0, "visibilities": M, "w_layers": nl, "fft_size": Np,
-                   "z_offset": not args.no_z_offset,
+                   "z_offset": not args.no_z_offset, "pass_layers": pass_layers,
+                   "workspace_bytes": ws32_bytes,
                    "step": "uvw binned once (grid_prepare), then one grid and one degrid of all visibilities on "
                            "that binning; separate_calls: the same two calls each binning uvw itself"},
         "roofline": roofline,
@@ -764,6 +802,7 @@ def main() -> int:
         "fp32_vs_fp64_rel_rms": acc,
         "stages": tab32,
         "separate_calls": separate,
+        "autotune": tuned,
         # each call separately: the sum of its stage times (HIP events, FP32)
         "stage_sum_ms_per_call": {c: sum(v["ms"] for k, v in separate["stages"].items() if k.startswith(c + "_"))
                                   for c in ("grid", "degrid")},

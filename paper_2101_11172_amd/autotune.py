@@ -5,7 +5,10 @@ the workspace it is given (grid_layers_per_pass).  More layers per pass means
 fewer, larger launches and more memory; fewer means more passes over the
 binned records.  ``tune_pass_layers`` times one batched grid plus one batched
 degrid for a few workspace sizes between the smallest the call accepts and a
-memory cap, and returns the fastest.  The 16 x 16 x 16 tile of the scatter and
+memory cap (or for every pass size), and returns the fastest.  Which is
+fastest depends on the workload: the 2048^2 wide-field call runs fastest in
+passes of 32 of its 49 layers, the 4096^2 imaging call in five passes, the
+batched channels in as few as the memory allows.  The 16 x 16 x 16 tile of the scatter and
 gather kernels is fixed at compile time by their LDS budget and is not tuned.
 
 Host logic and timing only: every call runs the library's own kernels.
@@ -17,8 +20,32 @@ import torch
 from . import wsgrid as wg
 
 
+def workspace_for_pass_layers(plan: "wg.Plan", prec: int, nch: int, M: int, layers: int) -> int:
+    """Smallest workspace whose layer passes hold at least `layers` layers
+    (all of them if fewer), found by bisection over grid_layers_per_pass."""
+    lo = wg.grid_workspace_bytes_batch(plan._p, prec, nch, M, True)
+    hi = wg.grid_workspace_bytes_batch(plan._p, prec, nch, M)
+    if wg.grid_layers_per_pass(plan._p, prec, nch, M, lo) >= layers:
+        return lo
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if wg.grid_layers_per_pass(plan._p, prec, nch, M, mid) >= layers:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def pass_sizes(plan: "wg.Plan", prec: int, nch: int, M: int) -> list:
+    """Every distinct layer-pass size of a call (whole tile layers, up to all)."""
+    full = wg.grid_workspace_bytes_batch(plan._p, prec, nch, M)
+    top = wg.grid_layers_per_pass(plan._p, prec, nch, M, full)
+    return sorted({min(top, 16 * k) for k in range(1, (top + 15) // 16 + 1)})
+
+
 def tune_pass_layers(plan: "wg.Plan", uvw: torch.Tensor, counts, vis: torch.Tensor, image: torch.Tensor,
-                     max_workspace_bytes: int, n_candidates: int = 4, repeats: int = 2) -> dict:
+                     max_workspace_bytes: int, n_candidates: int = 4, repeats: int = 2,
+                     every_pass_size: bool = False) -> dict:
     """Fastest workspace size (and its layers per pass) for these inputs.
 
     uvw, vis: concatenated channels (counts[c] visibilities each); image:
@@ -38,9 +65,13 @@ def tune_pass_layers(plan: "wg.Plan", uvw: torch.Tensor, counts, vis: torch.Tens
     top = min(wg.grid_workspace_bytes_batch(plan._p, prec, nch, M), int(max_workspace_bytes))
     if top < least:
         raise ValueError(f"the cap is below the smallest workspace ({least} bytes)")
-    sizes = sorted({least + (top - least) * i // max(1, n_candidates - 1) for i in range(n_candidates)})
+    if every_pass_size:      # each pass size within the cap, at its smallest workspace
+        sizes = [workspace_for_pass_layers(plan, prec, nch, M, n) for n in pass_sizes(plan, prec, nch, M)]
+        sizes = [b for b in sizes if b <= top] or [least]
+    else:
+        sizes = sorted({least + (top - least) * i // max(1, n_candidates - 1) for i in range(n_candidates)})
     by_layers = {}
-    for b in sizes:      # keep the smallest workspace that gives each pass size
+    for b in sorted(sizes):      # keep the smallest workspace that gives each pass size
         by_layers.setdefault(wg.grid_layers_per_pass(plan._p, prec, nch, M, b), b)
     stream = torch.cuda.current_stream(plan.device)
     dirty = torch.empty((nch, plan.N, plan.N), dtype=rdt, device=plan.device)

@@ -47,7 +47,7 @@ def test_workload_stats_match_brute_force(N, L, wmax, M):
 def test_counters_hold_for_their_workload_only(tmp_path, monkeypatch):
     # a counter summary is used only on the sources and the workload it was taken on
     (tmp_path / "profiles").mkdir()
-    key = bench.workload_key("widefield", 2048, 7, 0.25, 9999360, 49)
+    key = bench.workload_key("widefield", 2048, 7, 0.25, 9999360, 49, 32)
     t = {"source_digest": bench.source_digest(), "workload": key,
          "per_launch_bytes": {"grid_tiles:f32": 2.0e9}, "valu_per_launch": {"grid_tiles:f32": 1024 * 2.4e6}}
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(t))
@@ -56,7 +56,7 @@ def test_counters_hold_for_their_workload_only(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "source_digest", lambda: digest)
     assert bench.traffic_for("grid_tiles", "f32", key) == 2.0e9
     assert abs(bench.issue_for("grid_tiles", "f32", key)["valu_issue_ms"] - 4.0) < 1e-12
-    other = bench.workload_key("widefield3", 2048, 7, 1 / 3, 9999360, 39)
+    other = bench.workload_key("widefield3", 2048, 7, 1 / 3, 9999360, 39, 32)
     assert bench.traffic_for("grid_tiles", "f32", other) is None and bench.issue_for("grid_tiles", "f32", other) is None
     t["source_digest"] = "0" * 16
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(t))
