@@ -75,7 +75,7 @@ def workload_stats(uvw, N: int, L: float, W: int, x0: float, wmax: float, Np: in
             "tile_visits": visits, "nonempty_lines": row_lines, "lines": nl * Np}
 
 
-def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict) -> float:
+def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict, prepared: bool = False) -> float:
     """Algorithmic HBM bytes of one launch of a stage (what the stage must move)."""
     b = 16 if f64 else 8            # complex
     r = 8 if f64 else 4             # real
@@ -85,13 +85,14 @@ def stage_bytes(st: str, M: int, N: int, Np: int, nl: int, f64: bool, ws: dict) 
     sort = 2 * M * rec                                  # per-bin sort: records in and out
     return {
         "grid_bin": M * (2 * 24 + b + rec) + sort,      # uvw read twice, vis, records written, sorted
-        "grid_tiles": ws["tile_visits"] * rec + tiles,  # records in (once per tile reached), tiles out
+        # records in (once per tile reached), tiles out; on a shared binning each visit also
+        # reads the visibility the record names
+        "grid_tiles": ws["tile_visits"] * (rec + (b if prepared else 0)) + tiles,
         "grid_fft_v": tiles + inter_rows,               # occupied tiles in, lines of occupied rows out
         "grid_transpose": inter_rows + inter_rows,      # live lines in and out (the others are zero)
         "degrid_transpose": inter_rows + inter_rows,    # lines the transform along q needs, in and out
         "grid_fft_u": inter_rows + 2 * N * N * r,       # live intermediate, correction in, map out
         "degrid_bin": M * (2 * 24 + rec) + sort,
-        "grid_values": M * (rec + b + rec),             # shared binning: degrid record and vis in, grid record out
         "degrid_fft_p": 2 * N * N * r + inter_rows,     # image, correction in, live intermediate out
         "degrid_fft_q": inter_rows + tiles,             # intermediate rows in, occupied tiles out
         # tiles and records in, one part out per visit; then per record its parts in, the visibility out
@@ -295,7 +296,8 @@ def dft_errors(plan, w: dict, uvw, dev, n_pix: int = 10000, n_vis: int = 10000) 
     return out
 
 
-def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int, ws: dict, calls: int) -> dict:
+def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int, ws: dict, calls: int,
+                prepared: bool = False) -> dict:
     """Per call of grid or degrid: stage time (HIP events on the launch stream,
     summed over the stage's launches) and algorithmic bytes."""
     tab = {}
@@ -303,7 +305,7 @@ def stage_table(stages: dict, f64: bool, M: int, N: int, Np: int, nl: int, ws: d
         if n == 0:
             continue
         per = ms / calls
-        nbytes = stage_bytes(name, M, N, Np, nl, f64, ws)
+        nbytes = stage_bytes(name, M, N, Np, nl, f64, ws, prepared)
         tab[name] = {"ms": per, "launches_per_call": n / calls, "alg_bytes": nbytes,
                      "alg_GBps": nbytes / (per * 1e-3) / 1e9}
     return tab
@@ -711,7 +713,7 @@ def main() -> int:
     ms32 = timed_plain(step32, args.steps)
     _, stages32 = timed(step32, args.steps)
     log(f"fp32: {ms32:.3f} ms/step, {M / (ms32 * 1e-3):.4e} vis/s (one binning per step)")
-    tab32 = stage_table(stages32, False, M, N, Np, nl, ws, args.steps)
+    tab32 = stage_table(stages32, False, M, N, Np, nl, ws, args.steps, prepared=True)
     skipped = plan.skipped(wsgrid.WSG_F32)
     ms_sep = timed_plain(step32_separate, args.steps)
     _, stages_sep = timed(step32_separate, args.steps)
@@ -738,7 +740,7 @@ def main() -> int:
         _, stages64 = timed(step64, args.fp64_steps)
         log(f"fp64: {ms64:.3f} ms/step, {M / (ms64 * 1e-3):.4e} vis/s")
         fp64 = {"value": M / (ms64 * 1e-3), "ms_per_step": ms64,
-                "stages": stage_table(stages64, True, M, N, Np, nl, ws, args.fp64_steps)}
+                "stages": stage_table(stages64, True, M, N, Np, nl, ws, args.fp64_steps, prepared=True)}
         acc = {"grid": relrms(out_img32.double(), out_img64),
                "degrid": relrms(out_vis32.to(torch.complex128), out_vis64)}
 
@@ -765,7 +767,7 @@ def main() -> int:
         roofline["issue"] = {"valu_instr_per_call": issue["valu_instr_per_launch"] * n,
                              "valu_issue_ms": issue["valu_issue_ms"] * n,
                              "valu_issue_frac": issue["valu_issue_ms"] * n / d["ms"]}
-    total_alg = sum(stage_bytes(s, M, N, Np, nl, False, ws) for s in tab32)
+    total_alg = sum(stage_bytes(s, M, N, Np, nl, False, ws, prepared=True) for s in tab32)
     result = {
         "metric": (f"visibilities/s grid+degrid at W={W},x0={x0:g}, FP32 vs FP64"
                    + (", at <=1e-6 DFT error" if (W, x0) == (7, 0.25) else "")),

@@ -255,8 +255,8 @@ int degrid_visibilities_batch(const wsg_plan* plan, wsg_prec prec, int nch, cons
  *   degrid_visibilities_prepared: image [nch][N][N] real (prec) -> vis [sum M],
  * with the same ws, ws_bytes and prec.  Their results equal those of
  * grid_visibilities_batch / degrid_visibilities_batch on the prepared uvw
- * (degrid bit for bit; grid up to the rounding of the phase product, formed in
- * FP64 from the stored phase).  The binning stays valid until another call is
+ * (degrid bit for bit; grid up to the rounding of the value's phase product,
+ * which the scatter forms in FP64 from the stored phase).  The binning stays valid until another call is
  * made on ws: any grid_prepare or plain call of this plan on ws replaces it (the
  * library notices and the prepared calls then fail with WSG_EINVAL); calls of
  * other plans on the same memory are the caller's to avoid.  The plan keeps one
@@ -345,14 +345,13 @@ int64_t grid_last_skipped(const wsg_plan* plan);
  *   2 grid FFT pass along v (+ crop)             6 degrid FFT pass along q
  *   3 grid FFT pass along u (+ w-screen, sum)    7 degrid 3-D gather tiles
  *   8 grid intermediate transpose                9 degrid intermediate transpose
- *  10 grid values from a shared binning (grid_visibilities_prepared)
  * grid_prepare's binning is timed as stage 4 (it is the degridding binning).
  * wsg_stage_times() waits for the recorded events, writes the summed
  * milliseconds and the number of timed sections of the first n stages (one per
  * layer pass; stage 7 one more for the final sum of parts; either pointer may
  * be NULL), clears the record and returns WSG_NSTAGES (or < 0 on error).
  */
-#define WSG_NSTAGES 11
+#define WSG_NSTAGES 10
 void wsg_stage_timing(int enable);
 int wsg_stage_times(double* ms, int* launches, int n);
 

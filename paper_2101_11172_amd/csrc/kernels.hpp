@@ -328,27 +328,6 @@ __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __res
     }
 }
 
-// Gridding records from the degridding records of a shared binning (the fold,
-// coordinates, support boxes and phase depend on uvw alone): record i takes the
-// visibility it names, conjugated when folded (Sec. 5.4), times e^{+i 2 pi w
-// (n0 - 1)}, the conjugate of the degridding phase it holds (Alg. 5 step 2 and
-// Alg. 6 step 5 apply one phase with opposite signs).  The product is formed in
-// FP64.  n_rec: the number of records (device), at most M.
-template <typename R>
-__global__ void k_rec_values(const Rec<R>* __restrict__ rec, const uint32_t* __restrict__ n_rec, size_t M,
-                             const cpx<R>* __restrict__ vis, Rec<R>* __restrict__ out) {
-    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= M || i >= size_t(*n_rec)) return;
-    Rec<R> r = rec[i];
-    const cpx<R> V = vis[r.idx & 0x7fffffffu];
-    const double vx = double(V.x), vy = (r.idx & 0x80000000u) ? -double(V.y) : double(V.y);
-    const double co = double(r.v[0]), sn = -double(r.v[1]);
-    r.v[0] = R(vx * co - vy * sn);
-    r.v[1] = R(vx * sn + vy * co);
-    r.idx = 0;
-    out[i] = r;
-}
-
 // Second-level sort and touch classes.  With B = 17 - W, a record whose first
 // support index inside its tile is >= B along an axis also reaches the next
 // tile along that axis (W <= 16: never the one after).  Its touch class is the
@@ -657,14 +636,20 @@ struct __align__(16) ScatterStage {
     R wuv[ScatterCfg<R, W, WZ>::kSlots][3 * W];
 };
 
-template <typename R, int W, int WZ, bool SAME>
+// PREP: the records are those of a shared binning (degridding records: the
+// phase e^{-i 2 pi w (n0 - 1)} and the visibility index with the fold flag);
+// each record's value is then the visibility it names, conjugated when folded,
+// times the conjugate phase (formed in FP64), and the lane keeps two records
+// in flight so that the value's load (which needs the record's index) is
+// issued a round before its staging.
+template <typename R, int W, int WZ, bool SAME, bool PREP>
 __global__ void __launch_bounds__((ScatterCfg<R, W, WZ>::kThreads)) k_grid_tiles(const Rec<R>* __restrict__ rec,
                                                     const uint32_t* __restrict__ start,
                                                     const uint32_t* __restrict__ cls,
                                                     const uint32_t* __restrict__ tlist,
                                                     const uint32_t* __restrict__ tpos, DevParams P,
                                                     const R* __restrict__ coef_g, const R* __restrict__ coefz_g,
-                                                    cpx<R>* __restrict__ stack) {
+                                                    const cpx<R>* __restrict__ vis, cpx<R>* __restrict__ stack) {
     using Cfg = ScatterCfg<R, W, WZ>;
     constexpr int PI = Cfg::kPI, WB = Cfg::kWaveBatch, D = KernelDegree<R>::value;
     __shared__ R tre[Cfg::kCells];
@@ -787,8 +772,13 @@ __global__ void __launch_bounds__((ScatterCfg<R, W, WZ>::kThreads)) k_grid_tiles
         // move forward as vn grows by WB per round)
         uint32_t vn = q0 + uint32_t(rl);
         int g = 0;
-        Rec<R> nxt{};
+        Rec<R> nxt{}, nxt2{};
+        cpx<R> nval{R(0), R(0)};
         if (vn < q1) nxt = rec[seg_advance(sg, nseg, vn, g)];
+        if constexpr (PREP) {
+            if (vn < q1) nval = vis[nxt.idx & 0x7fffffffu];
+            if (vn + WB < q1) nxt2 = rec[seg_advance(sg, nseg, vn + WB, g)];
+        }
         for (uint32_t base = q0; base < q1; base += WB) {
             const int n = __builtin_amdgcn_readfirstlane(int(min(uint32_t(WB), q1 - base)));
             // support start of this lane's record, relative to the tile, packed
@@ -800,6 +790,13 @@ __global__ void __launch_bounds__((ScatterCfg<R, W, WZ>::kThreads)) k_grid_tiles
                 // stage: rotated weights, value folded into the u weights
                 const int pr = mod_w<W>(dr), ps = mod_w<W>(ds), pt = mod_w<WZ>(dt);
                 const int slot = slot0 + rl;
+                R v0 = nxt.v[0], v1 = nxt.v[1];
+                if constexpr (PREP) {
+                    const double vx = double(nval.x), vy = (nxt.idx & 0x80000000u) ? -double(nval.y) : double(nval.y);
+                    const double co = double(nxt.v[0]), sn = -double(nxt.v[1]);
+                    v0 = R(vx * co - vy * sn);
+                    v1 = R(vx * sn + vy * co);
+                }
 #pragma unroll
                 for (int i = 0; i < A0; ++i) {
                     const int a = i + half * A0;
@@ -823,8 +820,8 @@ __global__ void __launch_bounds__((ScatterCfg<R, W, WZ>::kThreads)) k_grid_tiles
                         int ku = pr + a, kv = ps + a;
                         ku -= ku >= W ? W : 0;
                         kv -= kv >= W ? W : 0;
-                        st.wuv[slot][ku] = nxt.v[0] * hu;
-                        st.wuv[slot][W + ku] = nxt.v[1] * hu;
+                        st.wuv[slot][ku] = v0 * hu;
+                        st.wuv[slot][W + ku] = v1 * hu;
                         st.wuv[slot][2 * W + kv] = hv;
                     }
                     if (a < WZ) {
@@ -842,7 +839,13 @@ __global__ void __launch_bounds__((ScatterCfg<R, W, WZ>::kThreads)) k_grid_tiles
             const uint64_t move_mask = __ballot(moved);
             wave_sync();
             vn += WB;
-            if (vn < q1) nxt = rec[seg_advance(sg, nseg, vn, g)];
+            if constexpr (PREP) {
+                nxt = nxt2;
+                if (vn < q1) nval = vis[nxt.idx & 0x7fffffffu];
+                if (vn + WB < q1) nxt2 = rec[seg_advance(sg, nseg, vn + WB, g)];
+            } else {
+                if (vn < q1) nxt = rec[seg_advance(sg, nseg, vn, g)];
+            }
 
             // groups of four slots with fixed offsets (one address update per
             // group); each slot's stage values are read while the previous

@@ -24,11 +24,14 @@ struct StageMark {
 bool tiles_supported(int W, int Wz, bool same);
 
 // One launch of the 3-D scatter (grid) or gather over the occupied tiles of a
-// layer pass; false when (W, Wz, same) is not compiled.
+// layer pass; false when (W, Wz, same) is not compiled.  vis (grid only):
+// non-null when rec holds a shared binning's degridding records, whose values
+// the scatter then takes from vis.
 template <typename R>
 bool launch_tiles(bool grid, int W, int Wz, bool same, int nblocks, const Rec<R>* rec, const uint32_t* start,
                   const uint32_t* cls, const uint32_t* tlist, const uint32_t* tpos, const DevParams& P,
-                  const R* coef, const R* coefz, cpx<R>* stack, cpx<R>* part, size_t part_stride, hipStream_t s);
+                  const R* coef, const R* coefz, const cpx<R>* vis, cpx<R>* stack, cpx<R>* part, size_t part_stride,
+                  hipStream_t s);
 
 // FFT lengths N' the passes are compiled for: 2^a and 3 2^a from 64 to 8192.
 bool fft_supported(int Np);

@@ -19,10 +19,13 @@ namespace wsg {
 template <typename R, int W, int WZ, bool SAME>
 void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* start, const uint32_t* cls,
                     const uint32_t* tlist, const uint32_t* tpos, const DevParams& P, const R* coef, const R* coefz,
-                    cpx<R>* stack, cpx<R>* part, size_t part_stride, hipStream_t s) {
-    if (grid)
-        hipLaunchKernelGGL((k_grid_tiles<R, W, WZ, SAME>), dim3(nblocks), dim3(ScatterCfg<R, W, WZ>::kThreads), 0, s,
-                           rec, start, cls, tlist, tpos, P, coef, coefz, stack);
+                    const cpx<R>* vis, cpx<R>* stack, cpx<R>* part, size_t part_stride, hipStream_t s) {
+    if (grid && vis)
+        hipLaunchKernelGGL((k_grid_tiles<R, W, WZ, SAME, true>), dim3(nblocks), dim3(ScatterCfg<R, W, WZ>::kThreads),
+                           0, s, rec, start, cls, tlist, tpos, P, coef, coefz, vis, stack);
+    else if (grid)
+        hipLaunchKernelGGL((k_grid_tiles<R, W, WZ, SAME, false>), dim3(nblocks), dim3(ScatterCfg<R, W, WZ>::kThreads),
+                           0, s, rec, start, cls, tlist, tpos, P, coef, coefz, (const cpx<R>*)nullptr, stack);
     else
         hipLaunchKernelGGL((k_degrid_tiles<R, W, WZ, SAME>), dim3(nblocks), dim3(256), 0, s, rec, start, cls, tlist,
                            tpos, P, coef, coefz, (const cpx<R>*)stack, part, part_stride);
@@ -31,14 +34,15 @@ void launch_tiles_w(bool grid, int nblocks, const Rec<R>* rec, const uint32_t* s
 template <typename R>
 bool launch_tiles(bool grid, int W, int Wz, bool same, int nblocks, const Rec<R>* rec, const uint32_t* start,
                   const uint32_t* cls, const uint32_t* tlist, const uint32_t* tpos, const DevParams& P,
-                  const R* coef, const R* coefz, cpx<R>* stack, cpx<R>* part, size_t part_stride, hipStream_t s) {
+                  const R* coef, const R* coefz, const cpx<R>* vis, cpx<R>* stack, cpx<R>* part, size_t part_stride,
+                  hipStream_t s) {
     if (same) {
         if (Wz != W) return false;
         switch (W) {
 #define WSG_SAME(w)                                                                                          \
     case w:                                                                                                   \
-        launch_tiles_w<R, w, w, true>(grid, nblocks, rec, start, cls, tlist, tpos, P, coef, coefz, stack, part, \
-                                      part_stride, s);                                                        \
+        launch_tiles_w<R, w, w, true>(grid, nblocks, rec, start, cls, tlist, tpos, P, coef, coefz, vis, stack,  \
+                                      part, part_stride, s);                                                  \
         return true;
             WSG_SAME_WIDTHS(WSG_SAME)
 #undef WSG_SAME
@@ -47,8 +51,8 @@ bool launch_tiles(bool grid, int W, int Wz, bool same, int nblocks, const Rec<R>
     }
 #define WSG_OWN(w, wz)                                                                                          \
     if (W == w && Wz == wz) {                                                                                 \
-        launch_tiles_w<R, w, wz, false>(grid, nblocks, rec, start, cls, tlist, tpos, P, coef, coefz, stack, part, \
-                                        part_stride, s);                                                        \
+        launch_tiles_w<R, w, wz, false>(grid, nblocks, rec, start, cls, tlist, tpos, P, coef, coefz, vis, stack, \
+                                        part, part_stride, s);                                                  \
         return true;                                                                                           \
     }
     WSG_OWN_Z_PAIRS(WSG_OWN)

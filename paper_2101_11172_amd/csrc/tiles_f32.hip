@@ -14,6 +14,6 @@ bool tiles_supported(int W, int Wz, bool same) {
 
 template bool launch_tiles<float>(bool, int, int, bool, int, const Rec<float>*, const uint32_t*, const uint32_t*,
                                   const uint32_t*, const uint32_t*, const DevParams&, const float*, const float*,
-                                  cpx<float>*, cpx<float>*, size_t, hipStream_t);
+                                  const cpx<float>*, cpx<float>*, cpx<float>*, size_t, hipStream_t);
 
 }  // namespace wsg

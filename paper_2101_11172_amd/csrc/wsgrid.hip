@@ -93,7 +93,7 @@ thread_local std::vector<StageEvent> g_events;
 namespace wsg {
 
 StageMark::StageMark(hipStream_t s_, int st) : s(s_), stage(st) {
-    static_assert(WSG_NSTAGES == 11, "stage ids are listed in wsgrid.h");
+    static_assert(WSG_NSTAGES == 10, "stage ids are listed in wsgrid.h");
     if (g_timing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
 }
 
@@ -348,7 +348,7 @@ void bin_stage(const wsg_plan* plan, bool grid, int stage, const int64_t* Mc, co
 // then the per-visibility finish into `out`).
 template <typename R>
 int pass_stage(const wsg_plan* plan, bool grid, const Rec<R>* rec, int64_t M, const void* in, void* out, void* ws,
-               const Layout& L, hipStream_t s) {
+               const Layout& L, hipStream_t s, const cpx<R>* prep_vis = nullptr) {
     DevParams P = dev_params(plan);
     P.nch = L.nch;
     char* w = static_cast<char*>(ws);
@@ -384,7 +384,7 @@ int pass_stage(const wsg_plan* plan, bool grid, const Rec<R>* rec, int64_t M, co
             {
                 StageMark mark(s, 1);
                 launch_tiles<R>(true, P.W, P.Wz, plan->same_design, nblocks, rec, start, cls, tlist, tpos, Q, coef,
-                                coefz, stack, nullptr, 0, s);
+                                coefz, prep_vis, stack, nullptr, 0, s);
             }
             launch_fft<R>(true, Q, occ, rows, stack, inter, inter2, tw, corr, nullptr,
                           static_cast<R*>(out), s);
@@ -394,8 +394,7 @@ int pass_stage(const wsg_plan* plan, bool grid, const Rec<R>* rec, int64_t M, co
             if (M > 0) {
                 StageMark mark(s, 7);
                 launch_tiles<R>(false, P.W, P.Wz, plan->same_design, nblocks, rec, start, cls, tlist, tpos, Q, coef,
-                                coefz, stack, part, size_t(M),
-                                s);
+                                coefz, nullptr, stack, part, size_t(M), s);
             }
         }
     }
@@ -419,22 +418,15 @@ int run(const wsg_plan* plan, bool grid, const int64_t* Mc, int64_t M, const dou
                          ws, L, s);
 }
 
-// Gridding from a shared binning: degrid records -> gridding records in the
-// unsorted-record buffer (free after the sort), then the layer passes on them.
+// Directions on a shared binning (the degridding records): degrid as usual;
+// grid with the scatter taking each record's value from the visibilities.
 template <typename R>
 int run_prepared(const wsg_plan* plan, bool grid, int64_t M, const void* in, void* out, void* ws, const Layout& L,
                  hipStream_t s) {
     char* w = static_cast<char*>(ws);
     const auto* rec = reinterpret_cast<const Rec<R>*>(w + L.rec);
     if (!grid) return pass_stage<R>(plan, false, rec, M, in, out, ws, L, s);
-    auto* grec = reinterpret_cast<Rec<R>*>(w + L.rec2);
-    if (M > 0) {
-        StageMark mark(s, 10);
-        hipLaunchKernelGGL(k_rec_values<R>, dim3(unsigned((M + 255) / 256)), dim3(256), 0, s, rec,
-                           reinterpret_cast<const uint32_t*>(w + L.start) + L.nbins, size_t(M),
-                           static_cast<const cpx<R>*>(in), grec);
-    }
-    return pass_stage<R>(plan, true, grec, M, in, out, ws, L, s);
+    return pass_stage<R>(plan, true, rec, M, in, out, ws, L, s, M > 0 ? static_cast<const cpx<R>*>(in) : nullptr);
 }
 
 template <typename T>

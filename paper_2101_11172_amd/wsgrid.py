@@ -315,7 +315,7 @@ def wsg_plan_params(N: int, L: float, W: int, x0: float, wmax: float, z_offset: 
 
 
 STAGES = ("grid_bin", "grid_tiles", "grid_fft_v", "grid_fft_u", "degrid_bin", "degrid_fft_p", "degrid_fft_q",
-          "degrid_tiles", "grid_transpose", "degrid_transpose", "grid_values")
+          "degrid_tiles", "grid_transpose", "degrid_transpose")
 
 
 def wsg_stage_timing(enable: bool) -> None:
