@@ -66,10 +66,21 @@ __device__ __forceinline__ bool axis_support(double xi, int W, double& nu, long 
     return true;
 }
 
+// The non-negative residue of the integer-valued f (|f| < 2^53) modulo n, in
+// FP64: the quotient's floor may be one off after rounding, which the two
+// corrections undo; q n and f - q n are exact.
+__device__ __forceinline__ int residue(double f, int n) {
+    const double dn = double(n);
+    const double q = floor(__ddiv_rn(f, dn));
+    double r = __dadd_rn(f, -__dmul_rn(q, dn));
+    if (r < 0.0) r += dn;
+    if (r >= dn) r -= dn;
+    return int(r);
+}
+
 // ch: the visibility's channel (virtual layer offset ch nbt kTileT)
-__device__ __forceinline__ bool vis_coords(const double* __restrict__ uvw, long long k, int ch,
-                                           const DevParams& P, VisCoords& c) {
-    double u = uvw[3 * k], v = uvw[3 * k + 1], w = uvw[3 * k + 2];
+__device__ __forceinline__ bool vis_coords_of(double u, double v, double w, int ch, const DevParams& P,
+                                              VisCoords& c) {
     if (!isfinite(u) || !isfinite(v) || !isfinite(w)) return false;
     c.folded = w < 0.0;
     if (c.folded) {
@@ -84,16 +95,20 @@ __device__ __forceinline__ bool vis_coords(const double* __restrict__ uvw, long 
     axis_support(up, P.W, c.nu_u, fu);
     axis_support(vp, P.W, c.nu_v, fv);
     axis_support(wp, P.Wz, c.nu_w, ft);
-    // the non-negative residues modulo N'
-    long long ru = fu % P.Np, rv = fv % P.Np;
-    c.ru = int(ru < 0 ? ru + P.Np : ru);
-    c.rv = int(rv < 0 ? rv + P.Np : rv);
+    // the non-negative residues modulo N' (|first| < 2^51 after the check above)
+    c.ru = residue(double(fu), P.Np);
+    c.rv = residue(double(fv), P.Np);
     long long it = ft - P.t_lo;
     if (P.tclamp && it == P.n_layers) it = P.n_layers - 1;      // w = wmax: the last bin is closed
     if (it < 0 || it > P.n_layers - P.Wz) return false;
     c.rt = int(it) + ch * P.nbt * kTileT;
     c.w = w;
     return true;
+}
+
+__device__ __forceinline__ bool vis_coords(const double* __restrict__ uvw, long long k, int ch,
+                                           const DevParams& P, VisCoords& c) {
+    return vis_coords_of(uvw[3 * k], uvw[3 * k + 1], uvw[3 * k + 2], ch, P, c);
 }
 
 __device__ __forceinline__ int bin_of(const VisCoords& c, const DevParams& P) {
@@ -172,11 +187,22 @@ static __global__ void __launch_bounds__(kAggThreads) k_bin_count(const double* 
     __syncthreads();
     const ChunkRange cr = chunk_of_block(coff, cblk, P.nch);
     uint32_t my_skipped = 0;
+    // the thread's coordinates, all loads in flight at once
+    double xu[kAggPer], xv[kAggPer], xw[kAggPer];
+#pragma unroll
+    for (int i = 0; i < kAggPer; ++i) {
+        const long long k = cr.k0 + (long long)i * kAggThreads + threadIdx.x;
+        const bool in = k < cr.k1;
+        xu[i] = in ? uvw[3 * k] : 0.0;
+        xv[i] = in ? uvw[3 * k + 1] : 0.0;
+        xw[i] = in ? uvw[3 * k + 2] : 0.0;
+    }
+#pragma unroll
     for (int i = 0; i < kAggPer; ++i) {
         const long long k = cr.k0 + (long long)i * kAggThreads + threadIdx.x;
         if (k >= cr.k1) break;
         VisCoords c;
-        if (!vis_coords(uvw, k, cr.ch, P, c)) {
+        if (!vis_coords_of(xu[i], xv[i], xw[i], cr.ch, P, c)) {
             ++my_skipped;
             continue;
         }
