@@ -304,6 +304,16 @@ __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __res
     __syncthreads();
     const ChunkRange cr = chunk_of_block(coff, cblk, P.nch);
     const long long k0 = cr.k0;
+    // the thread's coordinates, loaded once for both passes, all in flight at once
+    double xu[kAggPer], xv[kAggPer], xw[kAggPer];
+#pragma unroll
+    for (int i = 0; i < kAggPer; ++i) {
+        const long long k = k0 + (long long)i * kAggThreads + threadIdx.x;
+        const bool in = k < cr.k1;
+        xu[i] = in ? uvw[3 * k] : 0.0;
+        xv[i] = in ? uvw[3 * k + 1] : 0.0;
+        xw[i] = in ? uvw[3 * k + 2] : 0.0;
+    }
     // pass 1: rank of each visibility among this block's visibilities of its bin
     uint32_t tag[kAggPer];             // slot << 16 | rank; 0xffffffff: direct update
 #pragma unroll
@@ -311,7 +321,7 @@ __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __res
         tag[i] = 0xffffffffu;
         const long long k = k0 + (long long)i * kAggThreads + threadIdx.x;
         VisCoords c;
-        if (k < cr.k1 && vis_coords(uvw, k, cr.ch, P, c)) {
+        if (k < cr.k1 && vis_coords_of(xu[i], xv[i], xw[i], cr.ch, P, c)) {
             const int sl = agg_slot(T, bin_of(c, P));
             if (sl >= 0) tag[i] = (uint32_t(sl) << 16) | atomicAdd(&T.cnt[sl], 1u);
         }
@@ -326,7 +336,7 @@ __global__ void __launch_bounds__(kAggThreads) k_bin_scatter(const double* __res
     for (int i = 0; i < kAggPer; ++i) {
         const long long k = k0 + (long long)i * kAggThreads + threadIdx.x;
         VisCoords c;
-        if (!(k < cr.k1 && vis_coords(uvw, k, cr.ch, P, c))) continue;
+        if (!(k < cr.k1 && vis_coords_of(xu[i], xv[i], xw[i], cr.ch, P, c))) continue;
         const int b = bin_of(c, P);
         const uint32_t off = tag[i] != 0xffffffffu ? T.base[tag[i] >> 16] + (tag[i] & 0xffffu)
                                                    : atomicAdd(&cursor[b], 1u);
