@@ -61,3 +61,11 @@ def test_counters_hold_for_their_workload_only(tmp_path, monkeypatch):
     t["source_digest"] = "0" * 16
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(t))
     assert bench.traffic_for("grid_tiles", "f32", key) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    # one GPU is measured; a request for more exits with a message, before any device work
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
