@@ -169,3 +169,21 @@ def test_prepared_variants_match_plain(variant):
     rhs = float(np.sum(img.cpu().numpy() * g))
     assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
     plan.close()
+
+
+@pytest.mark.parametrize("W", [1, 3, 8, 12, 16])
+def test_prepared_widths_match_plain(W):
+    """Every scatter configuration on a shared binning: W <= 7 (16 records per
+    round, coefficients in registers), W = 8 (32 records per round, registers),
+    W >= 9 (32 per round, coefficients from memory), against the plain calls."""
+    N, L, x0, wmax, M = 64, 0.4, 0.25, 120.0, 2500
+    uvw = torch.from_numpy(inputs.uniform_uvw(M, 0.9 * N / (2 * L), wmax, 191 + W)).to(DEV)
+    for cdt, rdt, same in ((torch.complex128, torch.float64, 1e-13), (torch.complex64, torch.float32, 1e-6)):
+        vis = torch.from_numpy(inputs.random_vis(M, 192)).to(DEV, cdt)
+        img = torch.from_numpy(inputs.random_image(N, 193)).to(DEV, rdt)
+        plan = wg.Plan(N, L, W, x0, wmax, device=DEV)
+        g_plain, d_plain = plan.grid(uvw, vis).cpu().double().numpy(), plan.degrid(uvw, img).cpu()
+        plan.prepare(uvw, rdt)
+        g, d = plan.grid_prepared(vis).cpu().double().numpy(), plan.degrid_prepared(img).cpu()
+        assert torch.equal(d, d_plain) and rel(g, g_plain) <= same, (W, rdt, rel(g, g_plain))
+        plan.close()
