@@ -6,6 +6,8 @@
   (only this product enters the operators, see oracle.kernel_design);
 * argument validation.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -110,3 +112,19 @@ def test_axes_planner_rejects_bad_arguments():
         wg.wsg_plan_params_axes(64, 0.3, 7, 0.25, 8, 0.2, 100.0, wg.WSG_IMPROVED)   # W_z > W
     with pytest.raises(RuntimeError):
         wg.wsg_plan_params_axes(64, 0.3, 7, 0.25, 1, 0.2, 0.0, wg.WSG_ORIGINAL)     # no w range to bin
+
+
+def test_header_is_plain_c(tmp_path):
+    # the boundary is a C ABI: the header compiles as C99 and as C++ without warnings
+    import shutil
+    import subprocess
+    hdr = os.path.abspath(wg.HEADER)
+    src = tmp_path / "use.c"
+    src.write_text(f'#include "{hdr}"\nint main(void) {{ return WSG_NSTAGES == 10 ? 0 : 1; }}\n')
+    for cc, std in (("gcc", "-std=c99"), ("g++", "-std=c++17")):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} not available")
+        lang = ["-x", "c++"] if cc == "g++" else []
+        r = subprocess.run([cc, std, "-Wall", "-Wextra", "-Werror", *lang, "-c", str(src), "-o", str(tmp_path / "o")],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
