@@ -187,3 +187,28 @@ def test_prepared_widths_match_plain(W):
         g, d = plan.grid_prepared(vis).cpu().double().numpy(), plan.degrid_prepared(img).cpu()
         assert torch.equal(d, d_plain) and rel(g, g_plain) <= same, (W, rdt, rel(g, g_plain))
         plan.close()
+
+
+@pytest.mark.parametrize("rdt", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_prepared_empty_and_all_skipped(rdt):
+    """A binning of no visibilities, and one of visibilities all beyond wmax:
+    the prepared grid gives a zero map, the prepared degrid an empty output or
+    zeros, as the plain calls do."""
+    cdt = torch.complex128 if rdt == torch.float64 else torch.complex64
+    N, L, W, x0, wmax, M = 64, 0.3, 7, 0.25, 100.0, 500
+    plan = wg.Plan(N, L, W, x0, wmax, device=DEV)
+    img = torch.from_numpy(inputs.random_image(N, 201)).to(DEV, rdt)
+    none = torch.zeros((0, 3), dtype=torch.float64, device=DEV)
+    plan.prepare(none, rdt)
+    assert torch.count_nonzero(plan.grid_prepared(torch.zeros(0, dtype=cdt, device=DEV))).item() == 0
+    assert plan.degrid_prepared(img).numel() == 0
+    far = inputs.uniform_uvw(M, 0.9 * N / (2 * L), wmax, 202)
+    far[:, 2] = np.where(far[:, 2] >= 0, 1.5, -1.5) * wmax          # every |w| beyond wmax
+    t_far = torch.from_numpy(far).to(DEV)
+    vis = torch.from_numpy(inputs.random_vis(M, 203)).to(DEV, cdt)
+    plan.prepare(t_far, rdt)
+    assert wg.grid_last_skipped(plan._p) == M
+    assert torch.count_nonzero(plan.grid_prepared(vis)).item() == 0
+    d = plan.degrid_prepared(img)
+    assert d.shape == (M,) and torch.count_nonzero(d).item() == 0
+    plan.close()
