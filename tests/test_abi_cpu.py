@@ -35,7 +35,7 @@ def test_planner_matches_oracle(args, z_offset):
 
 
 @pytest.mark.parametrize("W,x0,tol", [(7, 0.25, 1e-12), (4, 0.25, 1e-12), (5, 0.2, 1e-12), (9, 0.25, 1e-11),
-                                      (4, 0.5, 1e-8)])
+                                      (10, 0.25, 1e-11), (4, 0.5, 1e-8)])
 def test_design_applies_same_product_as_oracle(W, x0, tol):
     nu = np.linspace(-0.5, 0.5, 41)
     x = np.linspace(-x0, x0, 33)

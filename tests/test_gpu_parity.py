@@ -86,6 +86,11 @@ CASES = [
     (64, 0.3, 8, 0.25, 100.0, 800, 0.9),      # W = 8: 64 residue pairs, one per lane
     (64, 0.3, 12, 0.25, 100.0, 800, 0.9),     # W = 12: three residue pairs per lane
     (64, 0.3, 16, 0.25, 100.0, 800, 0.9),     # W = 16: four pairs per lane, B = 1 (most records cross)
+    (64, 0.3, 10, 0.25, 100.0, 800, 0.9),     # the remaining accepted widths: two pairs per lane
+    (64, 0.3, 11, 0.25, 100.0, 800, 0.9),
+    (64, 0.3, 13, 0.25, 100.0, 800, 0.9),     # three pairs per lane
+    (64, 0.3, 14, 0.25, 100.0, 800, 0.9),     # four pairs per lane
+    (64, 0.3, 15, 0.25, 100.0, 800, 0.9),
 ]
 
 
