@@ -11,6 +11,8 @@ instantiations of the FFT passes that the small cases do not reach:
 * N' = 2048 (the low-cost setting: W = 4, x0 = 1/2, N = 2048, 25 layers), on
   every 100th visibility of the same tracks.
 * N' = 8192 (N = 2048, x0 = 1/8, W = 3, 3 layers), 40,000 uniform visibilities.
+* every other FFT length the library compiles (N' = 64, 96, 384, 768, 1536,
+  3072, 6144), on small cases of 4 layers.
 
 Tolerances: FP64 1e-10 (x0 = 1/2: 1e-7), FP32 1e-6, each with a max-abs
 check at 10x; at x0 = 1/2 the FP32 comparison follows test_gpu_parity.py
@@ -98,3 +100,14 @@ def test_fft_8192_against_oracle():
     assert op.Nprime == 8192 and op.n_layers == 3
     uvw = inputs.uniform_uvw(40000, 0.9 * N / (2 * L), wmax, 81)
     _compare("fft8192", N, L, W, x0, wmax, uvw, inputs.random_vis(40000, 82), inputs.random_image(N, 83))
+
+
+@pytest.mark.parametrize("Np", [64, 96, 384, 768, 1536, 3072, 6144])
+def test_every_other_fft_length_against_oracle(Np):
+    """The FFT lengths no other oracle case reaches (N' = 2^a and 3 2^a from 64
+    to 6144): N = N'/2 at x0 = 1/4, W = 4, 4 layers, 600 uniform visibilities."""
+    N, L, W, x0, wmax, M = Np // 2, 0.3, 4, 0.25, 20.0, 600
+    op = make_plan(N, L, W, x0, wmax)
+    assert op.Nprime == Np and op.n_layers == 4
+    uvw = inputs.uniform_uvw(M, 0.9 * N / (2 * L), wmax, 7)
+    _compare(f"fft{Np}", N, L, W, x0, wmax, uvw, inputs.random_vis(M, 8), inputs.random_image(N, 9))
