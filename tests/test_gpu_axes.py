@@ -54,8 +54,14 @@ def check(name, plan, uvw, vis, img, ref_g, ref_d, tol64=1e-10):
 
 @pytest.mark.parametrize("case", [(64, 0.3, 7, 0.25, 3, 0.2, 100.0, True), (64, 0.3, 7, 0.25, 1, 0.05, 60.0, True),
                                   (128, 0.4, 7, 0.25, 5, 0.25, 150.0, False), (64, 0.3, 4, 0.25, 1, 0.1, 50.0, True),
-                                  (64, 0.3, 7, 0.25, 7, 0.35, 100.0, True)],
-                         ids=["W7Wz3", "W7Wz1", "W7Wz5-nooff", "W4Wz1", "W7Wz7z0.35"])
+                                  (64, 0.3, 7, 0.25, 7, 0.35, 100.0, True),
+                                  # the remaining compiled pairs
+                                  (64, 0.3, 7, 0.25, 2, 0.1, 100.0, True), (64, 0.3, 7, 0.25, 4, 0.2, 100.0, True),
+                                  (64, 0.3, 7, 0.25, 6, 0.3, 100.0, True), (64, 0.3, 3, 0.25, 1, 0.1, 50.0, True),
+                                  (64, 0.3, 5, 0.25, 1, 0.1, 50.0, True), (64, 0.3, 6, 0.25, 1, 0.1, 50.0, True),
+                                  (64, 0.3, 8, 0.25, 1, 0.1, 50.0, True)],
+                         ids=["W7Wz3", "W7Wz1", "W7Wz5-nooff", "W4Wz1", "W7Wz7z0.35", "W7Wz2", "W7Wz4", "W7Wz6",
+                              "W3Wz1", "W5Wz1", "W6Wz1", "W8Wz1"])
 def test_own_w_axis_against_oracle(case):
     N, L, W, x0, Wz, z0, wmax, z_offset = case
     M = 1500

@@ -104,8 +104,10 @@ def test_fft_8192_against_oracle():
 
 @pytest.mark.parametrize("Np", [64, 96, 384, 768, 1536, 3072, 6144])
 def test_every_other_fft_length_against_oracle(Np):
-    """The FFT lengths no other oracle case reaches (N' = 2^a and 3 2^a from 64
-    to 6144): N = N'/2 at x0 = 1/4, W = 4, 4 layers, 600 uniform visibilities."""
+    """The compiled FFT lengths (N' = 2^a and 3 2^a from 64 to 6144) that the
+    x0 = 1/4 cases elsewhere do not reach (the 3 2^a ones also run at x0 = 1/3
+    in test_gpu_axes.py): N = N'/2 at x0 = 1/4, W = 4, 4 layers, 600 uniform
+    visibilities."""
     N, L, W, x0, wmax, M = Np // 2, 0.3, 4, 0.25, 20.0, 600
     op = make_plan(N, L, W, x0, wmax)
     assert op.Nprime == Np and op.n_layers == 4
